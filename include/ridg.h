@@ -1,0 +1,170 @@
+/*
+ * ridg.h - C ABI of the MI355X RIDG (regionally-implicit discontinuous Galerkin)
+ * predictor/corrector library (libridg.so, HIP kernels for gfx950).
+ *
+ * Method (arXiv 2101.01231): scalar conservation law q_t + div(v q) = 0
+ * (Sec. 2.1) on a uniform periodic Cartesian mesh of the unit box [0,1]^d,
+ * d = 1, 2, 3. Each step has two stages:
+ *   prediction (Sec. 2.2, eq. pred_full_system): for every element, the
+ *     space-time DG system on its region of 3^d vertex neighbours (upwind
+ *     fluxes on faces inside the region, the region element's own trace on
+ *     the region boundary, causal source from the state at t^n) is solved and
+ *     only the centre's space-time coefficients W are kept;
+ *   correction (Sec. 2.3): explicit flux-form update of every element's
+ *     modal coefficients from its own W and its face neighbours' W
+ *     (Rusanov flux, which for linear advection is exact upwinding).
+ * Region matrices are assembled quasi-quadrature-free (Sec. 3): the velocity
+ * is projected on the space-time basis and contracted with exact,
+ * precomputed Legendre triple-product tensors.
+ *
+ * Basis: orthonormal (w.r.t. the element average) scaled Legendre products of
+ * total degree <= order-1 in space (theta = C(order-1+d, d) modes) and in
+ * space-time (theta_T = C(order+d, d+1) modes).
+ *
+ * State layout (set/get): q[e * theta + k], element e = i0 + n0 (i1 + n1 i2)
+ * (x fastest), mode k ordered by total degree, then lexicographically
+ * descending in the exponents (a_1, ..., a_d): in 2D, order 3:
+ * 1, x, y, x^2, xy, y^2. Prediction layout (ridg_get_prediction):
+ * w[e * theta_T + k] with space-time exponents (b_t, b_1..b_d) ordered the
+ * same way (time exponent first).
+ *
+ * Conventions: every function returns 0 (RIDG_OK) on success, a negative
+ * RIDG_E_* code on error (the handle is left unchanged and
+ * ridg_last_error() describes the failure), or a positive RIDG_W_* warning
+ * (the call still did its work). All device work goes to the HIP stream
+ * given at creation; calls on one handle must not overlap from several host
+ * threads. Handles are independent of each other.
+ */
+#ifndef RIDG_H_
+#define RIDG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RIDG_ABI_VERSION 1
+
+/* return codes */
+#define RIDG_OK 0
+#define RIDG_E_INVAL (-1)       /* bad argument: dims, sizes, dt, null pointer, count mismatch */
+#define RIDG_E_NOMEM (-2)       /* workspace smaller than ridg_workspace_bytes() */
+#define RIDG_E_DEVICE (-3)      /* a HIP call failed (message in ridg_last_error) */
+#define RIDG_E_SINGULAR (-4)    /* zero pivot in a host FP64 factorisation */
+#define RIDG_E_NONFINITE (-5)   /* NaN/Inf in the input state */
+#define RIDG_E_UNSUPPORTED (-6) /* valid problem outside what the library implements */
+#define RIDG_W_UNSTABLE 1       /* CFL number dt*max|v_i|/h_i above 1: the step may be unstable */
+
+/* velocity field kinds */
+#define RIDG_FLUX_CONST 0    /* v = velocity[0..d-1] */
+#define RIDG_FLUX_ROTATION 1 /* 2D solid-body rotation v = (-(y - c_y), x - c_x), c = rot_center */
+#define RIDG_FLUX_AFFINE 2   /* v_i = velocity[i] + sum_j vel_grad[3 i + j] x_j, vel_grad[3 i + i] = 0 */
+
+/* arithmetic of the prediction (the correction is always FP64) */
+#define RIDG_FP64 0
+#define RIDG_FP32_REFINE 1 /* FP32 region solves + FP64-residual iterative refinement */
+
+/* region solver */
+#define RIDG_SOLVER_AUTO 0        /* PREFACTORED for RIDG_FLUX_CONST, REGION otherwise */
+#define RIDG_SOLVER_PREFACTORED 1 /* constant v only: W = G Q_region with G = E_c A^-1 C from a host FP64 LU */
+#define RIDG_SOLVER_REGION 2      /* per element: assemble (QQF) and solve the region system by upwind block
+                                     elimination with pivoted dense LU per block; regions whose centre lies on
+                                     a dependency cycle use the dense path */
+#define RIDG_SOLVER_DENSE 3       /* per element: dense pivoted LU of the whole 3^d theta_T region system */
+
+/* memory kinds for set/get */
+#define RIDG_HOST 0
+#define RIDG_DEVICE 1
+
+typedef struct ridg_problem {
+  int32_t dim;          /* d in {1, 2, 3} */
+  int32_t n[3];         /* elements per axis, n[i] >= 3 for i < dim (the 3^d region elements are distinct) */
+  int32_t order;        /* M >= 1: basis of total degree M-1; the library implements M <= 5 */
+  int32_t flux;         /* RIDG_FLUX_* */
+  double velocity[3];   /* CONST: v; AFFINE: constant part */
+  double rot_center[2]; /* ROTATION: centre; must lie on element boundaries (c_x n_x, c_y n_y integers) */
+  double vel_grad[9];   /* AFFINE: row-major dv_i/dx_j, diagonal must be 0 */
+  int32_t precision;    /* RIDG_FP64 or RIDG_FP32_REFINE */
+  int32_t refine_steps; /* FP32_REFINE: refinement sweeps 0..3 */
+  int32_t solver;       /* RIDG_SOLVER_* */
+  int32_t reserved;     /* must be 0 */
+} ridg_problem;
+
+typedef struct ridg_info {
+  int32_t abi_version;
+  int32_t theta;      /* spatial modes per element */
+  int32_t theta_t;    /* space-time modes per element */
+  int32_t solver;     /* resolved RIDG_SOLVER_* */
+  int64_t n_elements;
+  int64_t n_plans;          /* REGION: distinct upwind elimination plans */
+  int64_t n_dense_elements; /* REGION: elements solved by the dense path */
+  int64_t n_taps;           /* PREFACTORED: non-zero blocks of G (upwind cone) */
+  double flops_per_step;    /* arithmetic of the algorithm actually run (FMA = 2) */
+  double bytes_per_step;    /* algorithmic HBM bytes: state in/out + predictions out/in */
+} ridg_info;
+
+typedef struct ridg_handle ridg_t;
+
+/* Size in bytes of the device workspace ridg_create needs for this problem.
+ * Pure host function (no device calls); validates the problem. */
+int ridg_workspace_bytes(const ridg_problem* problem, size_t* bytes);
+
+/* Create a handle. d_workspace: device memory of at least ws_bytes =
+ * ridg_workspace_bytes(), allocated by the caller, 256-byte aligned, owned by
+ * the caller and borrowed until ridg_destroy. hip_stream: a hipStream_t (NULL
+ * = the default stream) on which all work of this handle is queued. Host-side
+ * FP64 precompute (exact reference tensors, elimination plans, prefactored
+ * operators) happens here. The state is zero after creation. */
+int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                ridg_t** out);
+
+/* Copy a state in (layout above). count must equal n_elements * theta. where:
+ * RIDG_HOST (pageable host memory; the call returns after the copy) or
+ * RIDG_DEVICE (device memory; queued on the stream). Non-finite host values
+ * give RIDG_E_NONFINITE and leave the state unchanged. */
+int ridg_set_state(ridg_t* h, const double* q, size_t count, int32_t where);
+
+/* Queue n_steps >= 0 RIDG steps of size dt > 0 on the stream (asynchronous).
+ * dt-dependent host tables are rebuilt when dt changes. Returns
+ * RIDG_W_UNSTABLE when the CFL number exceeds 1. */
+int ridg_step(ridg_t* h, int32_t n_steps, double dt);
+
+/* Copy the state out (layout above); synchronises the stream for RIDG_HOST. */
+int ridg_get_state(ridg_t* h, double* q, size_t count, int32_t where);
+
+/* The centre predictions W of the current state for step size dt, without the
+ * correction (count = n_elements * theta_T, layout above). */
+int ridg_get_prediction(ridg_t* h, double dt, double* w, size_t count, int32_t where);
+
+/* Sizes and cost model of the handle. */
+int ridg_get_info(ridg_t* h, ridg_info* info);
+
+/* Wait for all queued work of the handle. */
+int ridg_synchronize(ridg_t* h);
+
+/* Release the handle (not the workspace). NULL is accepted. */
+int ridg_destroy(ridg_t* h);
+
+/* Host-only inspection of the FP64 precompute (no device needed).
+ * Dense region matrix of element e for step dt as assembled by the library
+ * (QQF): size (3^d theta_T)^2, row-major, blocks ordered by region offset
+ * (o_1..o_d) in {-1,0,1}^d lexicographically with o_1 slowest, rows = test
+ * functions. count must equal the number of entries. */
+int ridg_host_region_matrix(const ridg_problem* problem, int64_t element, double dt, double* a,
+                            size_t count);
+
+/* Constant velocity: the prefactored prediction operator G (theta_T x 3^d
+ * theta, row-major, column blocks in the region-offset order above) such
+ * that W_e = G [Q_{e+o}]_o. */
+int ridg_host_prediction_operator(const ridg_problem* problem, double dt, double* g, size_t count);
+
+const char* ridg_error_string(int code);
+/* Message of the last error on the calling thread (empty if none). */
+const char* ridg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RIDG_H_ */

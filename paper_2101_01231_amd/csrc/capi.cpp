@@ -1,0 +1,538 @@
+// C ABI of libridg (declared in include/ridg.h): argument checking, workspace carving,
+// host precompute, and the step sequence (prediction, then correction) on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "ridg_internal.hpp"
+
+using namespace ridg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(int err, const char* what) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString((hipError_t)err));
+  return fail(RIDG_E_DEVICE, buf);
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
+
+struct Layout {
+  size_t q0, q1, w, stage, tens, g, taps, plans, items, item_plan, dense, scratch, flag, total;
+  int64_t n_items = 0, n_dense = 0, scratch_elems = 0;
+  size_t tens_doubles = 0;
+};
+
+size_t tensor_doubles(const RefTensors& T) {
+  return T.Tt.size() + T.Cc.size() + T.Bv.size() + T.Fo.size() + T.Fn.size() + T.Cv.size() + T.CFo.size() +
+         T.CFn.size();
+}
+
+// Element work lists of the REGION solver, grouped by plan and padded so that a wavefront never
+// mixes plans (padding repeats the group's last element with a "do not store" mark).
+void build_items(const RegionPlans& R, int ipw, std::vector<int32_t>* items, std::vector<int32_t>* item_plan) {
+  const int np = (int)R.plans.size();
+  std::vector<std::vector<int32_t>> groups(np);
+  for (size_t e = 0; e < R.elem_plan.size(); ++e)
+    if (R.elem_plan[e] >= 0) groups[R.elem_plan[e]].push_back((int32_t)e);
+  items->clear();
+  item_plan->clear();
+  for (int p = 0; p < np; ++p) {
+    auto& gr = groups[p];
+    if (gr.empty()) continue;
+    for (int32_t e : gr) {
+      items->push_back(e);
+      item_plan->push_back(p);
+    }
+    int32_t last = gr.back();
+    while (items->size() % ipw) {
+      items->push_back(-last - 1);
+      item_plan->push_back(p);
+    }
+  }
+}
+
+Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, int64_t n_items) {
+  Layout L;
+  const size_t nel = (size_t)P.nel, ns = T.ns, nt = T.nt;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes);
+    return at;
+  };
+  L.q0 = take(nel * ns * 8);
+  L.q1 = take(nel * ns * 8);
+  L.w = take(nel * nt * 8);
+  L.stage = take(nel * std::max(ns, nt) * 8);
+  L.tens_doubles = tensor_doubles(T);
+  L.tens = take(L.tens_doubles * 8);
+  L.g = take((size_t)kMaxBlocks * nt * ns * 8);
+  L.taps = take((size_t)kMaxBlocks * 3 * 4);
+  int64_t n_dense = 0;
+  size_t nplans = 0;
+  if (P.solver == RIDG_SOLVER_REGION && R) {
+    nplans = R->plans.size();
+    n_dense = (int64_t)R->dense_elems.size();
+  } else if (P.solver == RIDG_SOLVER_DENSE) {
+    n_dense = P.nel;
+  }
+  L.plans = take(std::max<size_t>(nplans, 1) * sizeof(PlanRec));
+  L.n_items = n_items;
+  L.items = take(std::max<int64_t>(n_items, 1) * 4);
+  L.item_plan = take(std::max<int64_t>(n_items, 1) * 4);
+  L.n_dense = n_dense;
+  L.dense = take(std::max<int64_t>(n_dense, 1) * 4);
+  const int64_t N = (int64_t)std::pow(3, P.d) * nt;
+  const int64_t per = N * (N + 1) * 8;
+  L.scratch_elems = n_dense > 0 ? std::max<int64_t>(1, std::min<int64_t>(n_dense, kDenseScratchBytes / per)) : 0;
+  L.scratch = take(std::max<int64_t>(L.scratch_elems, 1) * per);
+  L.flag = take(256);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+struct ridg_handle {
+  Problem P;
+  Basis B;
+  RefTensors T;
+  Layout L;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  double* Q[2] = {nullptr, nullptr};
+  int cur = 0;
+  double* W = nullptr;
+  double* stage = nullptr;
+  DevTensors dt{};
+  double* G = nullptr;
+  int32_t* taps = nullptr;
+  int ntaps = 0;
+  double g_dt = -1.0;
+  std::vector<int32_t> host_taps;
+  PlanRec* plans = nullptr;
+  int32_t* items = nullptr;
+  int32_t* item_plan = nullptr;
+  int32_t* dense = nullptr;
+  double* scratch = nullptr;
+  int32_t* flag = nullptr;
+  DevGeom geom{};
+  ridg_info info{};
+};
+
+namespace {
+
+int check_hip(int err, const char* what) { return err ? hip_fail(err, what) : RIDG_OK; }
+
+DevGeom make_geom(const Problem& P) {
+  DevGeom g{};
+  g.d = P.d;
+  g.n0 = P.n[0];
+  g.n1 = P.n[1];
+  g.n2 = P.n[2];
+  g.h0 = P.h[0];
+  g.h1 = P.h[1];
+  g.h2 = P.h[2];
+  for (int i = 0; i < 3; ++i) {
+    g.a[i] = P.vel.a[i];
+    for (int j = 0; j < 3; ++j) g.g[i][j] = P.vel.g[i][j];
+  }
+  return g;
+}
+
+double cfl_number(const Problem& P, double dt) {
+  // affine velocity: extremes over the unit box are at its corners
+  double best = 0.0;
+  for (int c = 0; c < (1 << P.d); ++c) {
+    for (int i = 0; i < P.d; ++i) {
+      double v = P.vel.a[i];
+      for (int j = 0; j < P.d; ++j) v += P.vel.g[i][j] * ((c >> j) & 1);
+      best = std::max(best, std::fabs(v) * dt / P.h[i]);
+    }
+  }
+  return best;
+}
+
+// flops of the algorithm as run (FMA = 2), per step
+double flops_model(const ridg_handle* h) {
+  const Problem& P = h->P;
+  const double nel = (double)P.nel, nt = h->T.nt, ns = h->T.ns, d = P.d;
+  const double np_active = (P.flux == RIDG_FLUX_CONST) ? 1.0 : (double)P.d;  // p-modes used per direction
+  double correct = nel * 2.0 * ns * nt * np_active * 3.0 * d;  // volume + 2 faces per direction
+  double predict = 0.0;
+  if (P.solver == RIDG_SOLVER_PREFACTORED) {
+    predict = nel * 2.0 * h->ntaps * nt * ns;
+  } else {
+    auto per_block = [&](int own_faces, int in_faces) {
+      double assembly = 2.0 * nt * nt * np_active * (d + own_faces);
+      double rhs = 2.0 * nt * ns + in_faces * 2.0 * nt * nt * np_active;
+      double lu = 2.0 / 3.0 * nt * nt * nt + 2.0 * nt * nt;  // elimination of [A|b] + back substitution
+      return assembly + rhs + lu;
+    };
+    double nbn = std::pow(3.0, d) * nt;
+    double dense_elem = 2.0 / 3.0 * nbn * nbn * nbn + 2.0 * nbn * nbn;
+    if (P.solver == RIDG_SOLVER_DENSE) {
+      predict = nel * dense_elem;
+    } else {
+      // count per plan block from the host plans (items include padding duplicates: use elements)
+      predict = (double)h->info.n_dense_elements * dense_elem;
+      // plan work is tallied in ridg_create (stored in info.flops_per_step beforehand)
+      predict += h->info.flops_per_step;
+    }
+  }
+  return predict + correct;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ridg_error_string(int code) {
+  switch (code) {
+    case RIDG_OK: return "ok";
+    case RIDG_E_INVAL: return "invalid argument";
+    case RIDG_E_NOMEM: return "workspace too small";
+    case RIDG_E_DEVICE: return "device error";
+    case RIDG_E_SINGULAR: return "singular region matrix";
+    case RIDG_E_NONFINITE: return "non-finite value";
+    case RIDG_E_UNSUPPORTED: return "unsupported problem";
+    case RIDG_W_UNSTABLE: return "CFL number above 1";
+    default: return "unknown code";
+  }
+}
+
+const char* ridg_last_error(void) { return g_last_error.c_str(); }
+
+int ridg_workspace_bytes(const ridg_problem* problem, size_t* bytes) {
+  if (!bytes) return fail(RIDG_E_INVAL, "bytes is NULL");
+  Problem P;
+  std::string msg;
+  int rc = resolve_problem(problem, &P, &msg);
+  if (rc) return fail(rc, msg);
+  Basis B = make_basis(P.d, P.M);
+  RefTensors T = make_tensors(B);
+  int64_t n_items = 0;
+  RegionPlans R;
+  if (P.solver == RIDG_SOLVER_REGION) {
+    R = build_plans(P);
+    std::vector<int32_t> items, item_plan;
+    build_items(R, items_per_wave(P.d, P.M), &items, &item_plan);
+    n_items = (int64_t)items.size();
+  }
+  *bytes = make_layout(P, T, &R, n_items).total;
+  return RIDG_OK;
+}
+
+int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes, void* hip_stream, ridg_t** out) {
+  if (!out) return fail(RIDG_E_INVAL, "out is NULL");
+  if (!d_workspace) return fail(RIDG_E_INVAL, "workspace is NULL");
+  if ((uintptr_t)d_workspace % kAlign) return fail(RIDG_E_INVAL, "workspace must be 256-byte aligned");
+  Problem P;
+  std::string msg;
+  int rc = resolve_problem(problem, &P, &msg);
+  if (rc) return fail(rc, msg);
+  ridg_handle* h = new (std::nothrow) ridg_handle();
+  if (!h) return fail(RIDG_E_NOMEM, "host allocation failed");
+  h->P = P;
+  h->B = make_basis(P.d, P.M);
+  h->T = make_tensors(h->B);
+  RegionPlans R;
+  std::vector<int32_t> items, item_plan;
+  double plan_flops = 0.0;
+  if (P.solver == RIDG_SOLVER_REGION) {
+    R = build_plans(P);
+    build_items(R, items_per_wave(P.d, P.M), &items, &item_plan);
+    // flop tally of the plan work actually run (per element, padding excluded)
+    const double nt = h->T.nt, ns = h->T.ns;
+    const double np_active = (P.flux == RIDG_FLUX_CONST) ? 1.0 : (double)P.d;
+    std::vector<double> per_plan(R.plans.size(), 0.0);
+    for (size_t p = 0; p < R.plans.size(); ++p) {
+      const PlanRec& pr = R.plans[p];
+      for (int b = 0; b < pr.nb; ++b) {
+        int own = 0, in = 0;
+        for (int f = 0; f < 2 * P.d; ++f) (pr.blk[b].src[f] == kOwn ? own : in)++;
+        per_plan[p] += 2.0 * nt * nt * np_active * (P.d + own) + 2.0 * nt * ns + in * 2.0 * nt * nt * np_active +
+                       2.0 / 3.0 * nt * nt * nt + 2.0 * nt * nt;
+      }
+    }
+    for (int32_t pid : R.elem_plan)
+      if (pid >= 0) plan_flops += per_plan[pid];
+  }
+  h->L = make_layout(P, h->T, &R, (int64_t)items.size());
+  if (ws_bytes < h->L.total) {
+    delete h;
+    return fail(RIDG_E_NOMEM, "workspace smaller than ridg_workspace_bytes()");
+  }
+  h->stream = (hipStream_t)hip_stream;
+  h->ws = (char*)d_workspace;
+  h->Q[0] = (double*)(h->ws + h->L.q0);
+  h->Q[1] = (double*)(h->ws + h->L.q1);
+  h->W = (double*)(h->ws + h->L.w);
+  h->stage = (double*)(h->ws + h->L.stage);
+  h->G = (double*)(h->ws + h->L.g);
+  h->taps = (int32_t*)(h->ws + h->L.taps);
+  h->plans = (PlanRec*)(h->ws + h->L.plans);
+  h->items = (int32_t*)(h->ws + h->L.items);
+  h->item_plan = (int32_t*)(h->ws + h->L.item_plan);
+  h->dense = (int32_t*)(h->ws + h->L.dense);
+  h->scratch = (double*)(h->ws + h->L.scratch);
+  h->flag = (int32_t*)(h->ws + h->L.flag);
+  // upload tensors
+  const RefTensors& T = h->T;
+  std::vector<double> tens;
+  tens.reserve(h->L.tens_doubles);
+  double* base = (double*)(h->ws + h->L.tens);
+  auto push = [&](const std::vector<double>& v) {
+    const double* at = base + tens.size();
+    tens.insert(tens.end(), v.begin(), v.end());
+    return at;
+  };
+  h->dt.Tt = push(T.Tt);
+  h->dt.Cc = push(T.Cc);
+  h->dt.Bv = push(T.Bv);
+  h->dt.Fo = push(T.Fo);
+  h->dt.Fn = push(T.Fn);
+  h->dt.Cv = push(T.Cv);
+  h->dt.CFo = push(T.CFo);
+  h->dt.CFn = push(T.CFn);
+  h->geom = make_geom(P);
+  int err = hipMemcpyAsync(base, tens.data(), tens.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err && P.solver == RIDG_SOLVER_REGION) {
+    if (!R.plans.empty())
+      err = hipMemcpyAsync(h->plans, R.plans.data(), R.plans.size() * sizeof(PlanRec), hipMemcpyHostToDevice, h->stream);
+    if (!err && !items.empty())
+      err = hipMemcpyAsync(h->items, items.data(), items.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (!err && !item_plan.empty())
+      err = hipMemcpyAsync(h->item_plan, item_plan.data(), item_plan.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (!err && !R.dense_elems.empty())
+      err = hipMemcpyAsync(h->dense, R.dense_elems.data(), R.dense_elems.size() * 4, hipMemcpyHostToDevice, h->stream);
+  } else if (!err && P.solver == RIDG_SOLVER_DENSE) {
+    std::vector<int32_t> all((size_t)P.nel);
+    for (int64_t e = 0; e < P.nel; ++e) all[(size_t)e] = (int32_t)e;
+    err = hipMemcpyAsync(h->dense, all.data(), all.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (!err) err = hipStreamSynchronize(h->stream);
+  }
+  if (!err) err = hipMemsetAsync(h->Q[0], 0, (size_t)P.nel * T.ns * 8, h->stream);
+  if (!err) err = hipStreamSynchronize(h->stream);  // host staging vectors go out of scope
+  if (err) {
+    delete h;
+    return hip_fail(err, "ridg_create upload");
+  }
+  h->cur = 0;
+  ridg_info& I = h->info;
+  I.abi_version = RIDG_ABI_VERSION;
+  I.theta = T.ns;
+  I.theta_t = T.nt;
+  I.solver = P.solver;
+  I.n_elements = P.nel;
+  I.n_plans = (int64_t)R.plans.size();
+  I.n_dense_elements = h->L.n_dense;
+  I.n_taps = 0;
+  I.flops_per_step = plan_flops;
+  if (P.solver == RIDG_SOLVER_PREFACTORED) {
+    PlanRec rec;
+    element_plan(P, 0, &rec);
+    I.n_taps = rec.nb;
+    h->ntaps = rec.nb;
+  }
+  I.flops_per_step = flops_model(h);
+  I.bytes_per_step = (double)P.nel * 8.0 * (2.0 * T.ns + 2.0 * T.nt);
+  *out = h;
+  return RIDG_OK;
+}
+
+int ridg_destroy(ridg_t* h) {
+  delete h;
+  return RIDG_OK;
+}
+
+int ridg_get_info(ridg_t* h, ridg_info* info) {
+  if (!h || !info) return fail(RIDG_E_INVAL, "NULL argument");
+  *info = h->info;
+  return RIDG_OK;
+}
+
+int ridg_synchronize(ridg_t* h) {
+  if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
+  return check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+}
+
+int ridg_set_state(ridg_t* h, const double* q, size_t count, int32_t where) {
+  if (!h || !q) return fail(RIDG_E_INVAL, "NULL argument");
+  const size_t want = (size_t)h->P.nel * h->T.ns;
+  if (count != want) return fail(RIDG_E_INVAL, "count must equal n_elements * theta");
+  if (where == RIDG_HOST) {
+    for (size_t i = 0; i < count; ++i)
+      if (!std::isfinite(q[i])) return fail(RIDG_E_NONFINITE, "state contains NaN or Inf");
+    int err = hipMemcpyAsync(h->stage, q, count * 8, hipMemcpyHostToDevice, h->stream);
+    if (!err) err = launch_aos_to_soa(h->stage, h->Q[h->cur], h->P.nel, h->T.ns, h->stream);
+    if (!err) err = hipStreamSynchronize(h->stream);
+    return check_hip(err, "ridg_set_state");
+  }
+  if (where == RIDG_DEVICE) {
+    int err = hipMemsetAsync(h->flag, 0, 4, h->stream);
+    if (!err) err = launch_check_finite(q, (int64_t)count, h->flag, h->stream);
+    int32_t flag = 0;
+    if (!err) err = hipMemcpyAsync(&flag, h->flag, 4, hipMemcpyDeviceToHost, h->stream);
+    if (!err) err = hipStreamSynchronize(h->stream);
+    if (err) return hip_fail(err, "ridg_set_state");
+    if (flag) return fail(RIDG_E_NONFINITE, "state contains NaN or Inf");
+    return check_hip(launch_aos_to_soa(q, h->Q[h->cur], h->P.nel, h->T.ns, h->stream), "ridg_set_state");
+  }
+  return fail(RIDG_E_INVAL, "where must be RIDG_HOST or RIDG_DEVICE");
+}
+
+int ridg_get_state(ridg_t* h, double* q, size_t count, int32_t where) {
+  if (!h || !q) return fail(RIDG_E_INVAL, "NULL argument");
+  const size_t want = (size_t)h->P.nel * h->T.ns;
+  if (count != want) return fail(RIDG_E_INVAL, "count must equal n_elements * theta");
+  if (where == RIDG_HOST) {
+    int err = launch_soa_to_aos(h->Q[h->cur], h->stage, h->P.nel, h->T.ns, h->stream);
+    if (!err) err = hipMemcpyAsync(q, h->stage, count * 8, hipMemcpyDeviceToHost, h->stream);
+    if (!err) err = hipStreamSynchronize(h->stream);
+    return check_hip(err, "ridg_get_state");
+  }
+  if (where == RIDG_DEVICE)
+    return check_hip(launch_soa_to_aos(h->Q[h->cur], q, h->P.nel, h->T.ns, h->stream), "ridg_get_state");
+  return fail(RIDG_E_INVAL, "where must be RIDG_HOST or RIDG_DEVICE");
+}
+
+static int ensure_dt_tables(ridg_t* h, double dt) {
+  if (h->P.solver != RIDG_SOLVER_PREFACTORED || dt == h->g_dt) return RIDG_OK;
+  Prefactored pf;
+  std::string msg;
+  int rc = build_prefactored(h->P, h->T, dt, &pf, &msg);
+  if (rc) return fail(rc, msg);
+  h->host_taps.assign(pf.offs.size() * 3, 0);
+  for (size_t t = 0; t < pf.offs.size(); ++t)
+    for (int i = 0; i < 3; ++i) h->host_taps[3 * t + i] = pf.offs[t][i];
+  h->ntaps = (int)pf.offs.size();
+  int err = hipMemcpyAsync(h->G, pf.G.data(), pf.G.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipStreamSynchronize(h->stream);
+  if (err) return hip_fail(err, "upload of G");
+  h->g_dt = dt;
+  return RIDG_OK;
+}
+
+static int run_predict(ridg_t* h, const double* Q, double dt) {
+  const Problem& P = h->P;
+  int err = 0;
+  if (P.solver == RIDG_SOLVER_PREFACTORED) {
+    err = launch_predict_prefactored(P.d, P.M, h->geom, Q, h->W, h->G, h->host_taps.data(), h->ntaps, h->stream);
+  } else if (P.solver == RIDG_SOLVER_REGION) {
+    if (h->L.n_items)
+      err = launch_predict_plans(P.d, P.M, P.precision, P.refine, h->geom, dt, Q, h->W, h->dt, h->plans, h->items,
+                                 h->item_plan, h->L.n_items, h->stream);
+    if (!err && h->L.n_dense)
+      err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
+                                 h->L.scratch_elems, h->stream);
+  } else {
+    err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
+                               h->L.scratch_elems, h->stream);
+  }
+  return err ? hip_fail(err, "prediction launch") : RIDG_OK;
+}
+
+int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
+  if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
+  if (n_steps < 0) return fail(RIDG_E_INVAL, "n_steps must be >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be positive and finite");
+  if (n_steps == 0) return RIDG_OK;
+  if (h->P.solver == RIDG_SOLVER_REGION && h->P.d == 3 && h->T.nt > 64)
+    return fail(RIDG_E_UNSUPPORTED, "REGION solver supports theta_T <= 64");
+  int rc = ensure_dt_tables(h, dt);
+  if (rc) return rc;
+  for (int s = 0; s < n_steps; ++s) {
+    rc = run_predict(h, h->Q[h->cur], dt);
+    if (rc) return rc;
+    int err = launch_correct(h->P.d, h->P.M, h->P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt,
+                             h->stream);
+    if (err) return hip_fail(err, "correction launch");
+    h->cur ^= 1;
+  }
+  return cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;
+}
+
+int ridg_get_prediction(ridg_t* h, double dt, double* w, size_t count, int32_t where) {
+  if (!h || !w) return fail(RIDG_E_INVAL, "NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be positive and finite");
+  const size_t want = (size_t)h->P.nel * h->T.nt;
+  if (count != want) return fail(RIDG_E_INVAL, "count must equal n_elements * theta_T");
+  if (where != RIDG_HOST && where != RIDG_DEVICE) return fail(RIDG_E_INVAL, "where must be RIDG_HOST or RIDG_DEVICE");
+  if (h->P.solver == RIDG_SOLVER_REGION && h->P.d == 3 && h->T.nt > 64)
+    return fail(RIDG_E_UNSUPPORTED, "REGION solver supports theta_T <= 64");
+  int rc = ensure_dt_tables(h, dt);
+  if (rc) return rc;
+  rc = run_predict(h, h->Q[h->cur], dt);
+  if (rc) return rc;
+  if (where == RIDG_DEVICE)
+    return check_hip(launch_soa_to_aos(h->W, w, h->P.nel, h->T.nt, h->stream), "ridg_get_prediction");
+  int err = launch_soa_to_aos(h->W, h->stage, h->P.nel, h->T.nt, h->stream);
+  if (!err) err = hipMemcpyAsync(w, h->stage, count * 8, hipMemcpyDeviceToHost, h->stream);
+  if (!err) err = hipStreamSynchronize(h->stream);
+  return check_hip(err, "ridg_get_prediction");
+}
+
+int ridg_host_region_matrix(const ridg_problem* problem, int64_t element, double dt, double* a, size_t count) {
+  Problem P;
+  std::string msg;
+  int rc = resolve_problem(problem, &P, &msg);
+  if (rc) return fail(rc, msg);
+  if (!a) return fail(RIDG_E_INVAL, "a is NULL");
+  if (element < 0 || element >= P.nel) return fail(RIDG_E_INVAL, "element out of range");
+  if (!std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt not finite");
+  Basis B = make_basis(P.d, P.M);
+  RefTensors T = make_tensors(B);
+  auto offs = region_offsets(P.d);
+  const size_t n = offs.size() * T.nt;
+  if (count != n * n) return fail(RIDG_E_INVAL, "count must equal (3^d theta_T)^2");
+  std::vector<double> A;
+  assemble_region(P, T, element, dt, offs, &A);
+  std::memcpy(a, A.data(), n * n * 8);
+  return RIDG_OK;
+}
+
+int ridg_host_prediction_operator(const ridg_problem* problem, double dt, double* g, size_t count) {
+  Problem P;
+  std::string msg;
+  int rc = resolve_problem(problem, &P, &msg);
+  if (rc) return fail(rc, msg);
+  if (P.flux != RIDG_FLUX_CONST) return fail(RIDG_E_INVAL, "prediction operator needs a constant velocity");
+  if (!g) return fail(RIDG_E_INVAL, "g is NULL");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be finite and >= 0");
+  Basis B = make_basis(P.d, P.M);
+  RefTensors T = make_tensors(B);
+  auto offs = region_offsets(P.d);
+  const size_t nb = offs.size(), cols = nb * T.ns;
+  if (count != (size_t)T.nt * cols) return fail(RIDG_E_INVAL, "count must equal theta_T * 3^d * theta");
+  Prefactored pf;
+  rc = build_prefactored(P, T, dt, &pf, &msg);
+  if (rc) return fail(rc, msg);
+  std::memset(g, 0, count * 8);
+  for (size_t t = 0; t < pf.offs.size(); ++t) {
+    int code = 0;
+    for (int i = 0; i < P.d; ++i) code = code * 3 + (pf.offs[t][i] + 1);
+    for (int k = 0; k < T.nt; ++k)
+      for (int l = 0; l < T.ns; ++l)
+        g[(size_t)k * cols + (size_t)code * T.ns + l] = pf.G[((size_t)t * T.nt + k) * T.ns + l];
+  }
+  return RIDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,672 @@
+// Host FP64 precompute of libridg: exact Legendre tensors (quasi-quadrature-free
+// assembly, Sec. 3 of arXiv 2101.01231), velocity projection, face upwinding,
+// upwind elimination plans of the regions (Sec. 2.2), region assembly and the
+// prefactored constant-velocity prediction operator.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+#include "ridg_internal.hpp"
+
+namespace ridg {
+
+// ---------------------------------------------------------------- basis
+static std::vector<std::array<int, 4>> graded_indices(int nvar, int M) {
+  std::vector<std::array<int, 4>> out;
+  int e[4] = {0, 0, 0, 0};
+  // enumerate all tuples in [0, M)^nvar with sum <= M-1
+  int total = 1;
+  for (int i = 0; i < nvar; ++i) total *= M;
+  for (int code = 0; code < total; ++code) {
+    int c = code, s = 0;
+    for (int i = nvar - 1; i >= 0; --i) {
+      e[i] = c % M;
+      c /= M;
+      s += e[i];
+    }
+    if (s > M - 1) continue;
+    out.push_back({e[0], e[1], e[2], e[3]});
+  }
+  std::sort(out.begin(), out.end(), [nvar](const std::array<int, 4>& x, const std::array<int, 4>& y) {
+    int sx = 0, sy = 0;
+    for (int i = 0; i < nvar; ++i) {
+      sx += x[i];
+      sy += y[i];
+    }
+    if (sx != sy) return sx < sy;
+    for (int i = 0; i < nvar; ++i)
+      if (x[i] != y[i]) return x[i] > y[i];  // descending lexicographic
+    return false;
+  });
+  return out;
+}
+
+Basis make_basis(int d, int M) {
+  Basis b;
+  b.d = d;
+  b.M = M;
+  b.sidx = graded_indices(d, M);
+  b.tidx = graded_indices(d + 1, M);
+  b.theta = (int)b.sidx.size();
+  b.theta_t = (int)b.tidx.size();
+  return b;
+}
+
+// ---------------------------------------------------------------- exact 1D integrals
+// Linearisation of Legendre products (Adams-Neumann):
+//   P_m P_n = sum_k A(m,n,k) P_{m+n-2k},
+//   A = a(m-k) a(k) a(n-k) / a(m+n-k) * (2m+2n-4k+1) / (2m+2n-2k+1),  a(r) = (2r-1)!! / r!.
+static long double lin_a(int r) {
+  long double v = 1.0L;
+  for (int j = 1; j <= r; ++j) v *= (long double)(2 * j - 1) / (long double)j;
+  return v;
+}
+
+static long double leg_triple_unnormalised(int a, int b, int c) {
+  // int P_a P_b P_c over [-1, 1]
+  if ((a + b + c) % 2) return 0.0L;
+  if (c > a + b || c < std::abs(a - b)) return 0.0L;
+  int k = (a + b - c) / 2;
+  long double A = lin_a(a - k) * lin_a(k) * lin_a(b - k) / lin_a(a + b - k) *
+                  (long double)(2 * a + 2 * b - 4 * k + 1) / (long double)(2 * a + 2 * b - 2 * k + 1);
+  return A * 2.0L / (long double)(2 * c + 1);
+}
+
+double leg_t3(int a, int b, int c) {
+  long double nrm = sqrtl((long double)(2 * a + 1) * (2 * b + 1) * (2 * c + 1));
+  return (double)(nrm * leg_triple_unnormalised(a, b, c));
+}
+
+double leg_d3(int a, int b, int c) {
+  // P_a' = sum_{j < a, a - j odd} (2j + 1) P_j
+  long double s = 0.0L;
+  for (int j = a - 1; j >= 0; j -= 2) s += (long double)(2 * j + 1) * leg_triple_unnormalised(j, b, c);
+  long double nrm = sqrtl((long double)(2 * a + 1) * (2 * b + 1) * (2 * c + 1));
+  return (double)(nrm * s);
+}
+
+double leg_dm(int a, int b) {
+  if (b < a && ((a + b) % 2) == 1) return 2.0 * std::sqrt((double)(2 * a + 1) * (2 * b + 1));
+  return 0.0;
+}
+
+double leg_end(int m, int s) {
+  double v = std::sqrt((double)(2 * m + 1));
+  return (s < 0 && (m % 2)) ? -v : v;
+}
+
+// ---------------------------------------------------------------- reference tensors
+RefTensors make_tensors(const Basis& B) {
+  RefTensors T;
+  const int d = B.d, nt = B.theta_t, ns = B.theta, np = d + 1;
+  T.d = d;
+  T.nt = nt;
+  T.ns = ns;
+  T.np = np;
+  const double vol = std::ldexp(1.0, d);  // int over [-1,1]^d of 1
+  T.Tt.assign((size_t)nt * nt, 0.0);
+  T.Cc.assign((size_t)nt * ns, 0.0);
+  for (int k = 0; k < nt; ++k) {
+    const auto& bk = B.tidx[k];
+    for (int l = 0; l < nt; ++l) {
+      const auto& bl = B.tidx[l];
+      bool same_space = true;
+      for (int i = 1; i <= d; ++i) same_space &= (bk[i] == bl[i]);
+      if (!same_space) continue;
+      // int Psi_k(1) Psi_l(1) dxi - int int d_tau Psi_k Psi_l = 2^d [psi(1) psi(1) - int psi_k' psi_l]
+      T.Tt[(size_t)k * nt + l] = vol * (leg_end(bk[0], 1) * leg_end(bl[0], 1) - leg_dm(bk[0], bl[0]));
+    }
+    for (int l = 0; l < ns; ++l) {
+      const auto& al = B.sidx[l];
+      bool same = true;
+      for (int i = 0; i < d; ++i) same &= (bk[i + 1] == al[i]);
+      if (same) T.Cc[(size_t)k * ns + l] = vol * leg_end(bk[0], -1);
+    }
+  }
+  // p-mode exponent on spatial axis m
+  auto pexp = [](int p, int m) { return (p == 1 + m) ? 1 : 0; };
+  T.Bv.assign((size_t)d * np * nt * nt, 0.0);
+  T.Fo.assign((size_t)d * 2 * np * nt * nt, 0.0);
+  T.Fn.assign((size_t)d * 2 * np * nt * nt, 0.0);
+  T.Cv.assign((size_t)d * np * ns * nt, 0.0);
+  T.CFo.assign((size_t)d * 2 * np * ns * nt, 0.0);
+  T.CFn.assign((size_t)d * 2 * np * ns * nt, 0.0);
+  for (int i = 0; i < d; ++i) {
+    for (int p = 0; p < np; ++p) {
+      if (p == 1 + i) continue;  // nu_i does not depend on xi_i
+      for (int k = 0; k < nt; ++k) {
+        const auto& bk = B.tidx[k];
+        for (int l = 0; l < nt; ++l) {
+          const auto& bl = B.tidx[l];
+          // time axis: int psi_k0 psi_0 psi_l0 = 2 delta
+          double tt = leg_t3(bk[0], 0, bl[0]);
+          if (tt == 0.0) continue;
+          double v = tt, fo[2] = {tt, tt}, fn[2] = {tt, tt};
+          for (int m = 0; m < d; ++m) {
+            int a = bk[m + 1], c = bl[m + 1], q = pexp(p, m);
+            if (m == i) {
+              v *= leg_d3(a, q, c);
+              for (int s = 0; s < 2; ++s) {
+                int sg = s ? 1 : -1;
+                fo[s] *= sg * leg_end(a, sg) * leg_end(c, sg);
+                fn[s] *= sg * leg_end(a, sg) * leg_end(c, -sg);
+              }
+            } else {
+              double t3 = leg_t3(a, q, c);
+              v *= t3;
+              fo[0] *= t3;
+              fo[1] *= t3;
+              fn[0] *= t3;
+              fn[1] *= t3;
+            }
+          }
+          T.Bv[T.bv(i, p) + (size_t)k * nt + l] = v;
+          for (int s = 0; s < 2; ++s) {
+            int sg = s ? 1 : -1;
+            T.Fo[T.f(i, sg, p) + (size_t)k * nt + l] = fo[s];
+            T.Fn[T.f(i, sg, p) + (size_t)k * nt + l] = fn[s];
+          }
+        }
+      }
+      for (int k = 0; k < ns; ++k) {
+        const auto& ak = B.sidx[k];
+        for (int l = 0; l < nt; ++l) {
+          const auto& bl = B.tidx[l];
+          double tt = leg_t3(0, 0, bl[0]);  // Phi has no time dependence
+          if (tt == 0.0) continue;
+          double v = tt, fo[2] = {tt, tt}, fn[2] = {tt, tt};
+          for (int m = 0; m < d; ++m) {
+            int a = ak[m], c = bl[m + 1], q = pexp(p, m);
+            if (m == i) {
+              v *= leg_d3(a, q, c);
+              for (int s = 0; s < 2; ++s) {
+                int sg = s ? 1 : -1;
+                fo[s] *= sg * leg_end(a, sg) * leg_end(c, sg);
+                fn[s] *= sg * leg_end(a, sg) * leg_end(c, -sg);
+              }
+            } else {
+              double t3 = leg_t3(a, q, c);
+              v *= t3;
+              fo[0] *= t3;
+              fo[1] *= t3;
+              fn[0] *= t3;
+              fn[1] *= t3;
+            }
+          }
+          T.Cv[T.cv(i, p) + (size_t)k * nt + l] = v;
+          for (int s = 0; s < 2; ++s) {
+            int sg = s ? 1 : -1;
+            T.CFo[T.cf(i, sg, p) + (size_t)k * nt + l] = fo[s];
+            T.CFn[T.cf(i, sg, p) + (size_t)k * nt + l] = fn[s];
+          }
+        }
+      }
+    }
+  }
+  return T;
+}
+
+// ---------------------------------------------------------------- problem / velocity
+int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
+  if (!p) {
+    *msg = "problem is NULL";
+    return RIDG_E_INVAL;
+  }
+  Problem P;
+  P.d = p->dim;
+  if (P.d < 1 || P.d > 3) {
+    *msg = "dim must be 1, 2 or 3";
+    return RIDG_E_INVAL;
+  }
+  P.nel = 1;
+  for (int i = 0; i < 3; ++i) {
+    if (i < P.d) {
+      if (p->n[i] < 3) {
+        *msg = "n[i] must be >= 3 (the 3^d region elements must be distinct)";
+        return RIDG_E_INVAL;
+      }
+      if (p->n[i] > (1 << 20)) {
+        *msg = "n[i] too large";
+        return RIDG_E_INVAL;
+      }
+      P.n[i] = p->n[i];
+      P.h[i] = 1.0 / p->n[i];
+      P.nel *= p->n[i];
+    } else {
+      P.n[i] = 1;
+      P.h[i] = 1.0;
+    }
+  }
+  if (P.nel > (int64_t)1 << 31) {
+    *msg = "more than 2^31 elements";
+    return RIDG_E_INVAL;
+  }
+  P.M = p->order;
+  if (P.M < 1) {
+    *msg = "order must be >= 1";
+    return RIDG_E_INVAL;
+  }
+  if (P.M > kMaxOrder) {
+    *msg = "order above 5 is not implemented";
+    return RIDG_E_UNSUPPORTED;
+  }
+  if (p->reserved != 0) {
+    *msg = "reserved must be 0";
+    return RIDG_E_INVAL;
+  }
+  P.flux = p->flux;
+  Affine& v = P.vel;
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(p->velocity[i])) {
+      *msg = "velocity not finite";
+      return RIDG_E_INVAL;
+    }
+  if (P.flux == RIDG_FLUX_CONST) {
+    for (int i = 0; i < P.d; ++i) v.a[i] = p->velocity[i];
+  } else if (P.flux == RIDG_FLUX_ROTATION) {
+    if (P.d != 2) {
+      *msg = "RIDG_FLUX_ROTATION needs dim == 2";
+      return RIDG_E_INVAL;
+    }
+    double cx = p->rot_center[0], cy = p->rot_center[1];
+    if (!std::isfinite(cx) || !std::isfinite(cy)) {
+      *msg = "rot_center not finite";
+      return RIDG_E_INVAL;
+    }
+    // v = (-(y - cy), x - cx) = (cy, -cx) + [[0, -1], [1, 0]] x
+    v.a[0] = cy;
+    v.a[1] = -cx;
+    v.g[0][1] = -1.0;
+    v.g[1][0] = 1.0;
+  } else if (P.flux == RIDG_FLUX_AFFINE) {
+    for (int i = 0; i < P.d; ++i) {
+      v.a[i] = p->velocity[i];
+      for (int j = 0; j < P.d; ++j) {
+        double gij = p->vel_grad[3 * i + j];
+        if (!std::isfinite(gij)) {
+          *msg = "vel_grad not finite";
+          return RIDG_E_INVAL;
+        }
+        if (i == j && gij != 0.0) {
+          *msg = "vel_grad diagonal must be zero (v_i independent of x_i)";
+          return RIDG_E_INVAL;
+        }
+        v.g[i][j] = gij;
+      }
+    }
+  } else {
+    *msg = "unknown flux kind";
+    return RIDG_E_INVAL;
+  }
+  P.precision = p->precision;
+  if (P.precision != RIDG_FP64 && P.precision != RIDG_FP32_REFINE) {
+    *msg = "unknown precision";
+    return RIDG_E_INVAL;
+  }
+  P.refine = p->refine_steps;
+  if (P.refine < 0 || P.refine > 3) {
+    *msg = "refine_steps must be in 0..3";
+    return RIDG_E_INVAL;
+  }
+  int solver = p->solver;
+  if (solver == RIDG_SOLVER_AUTO) solver = (P.flux == RIDG_FLUX_CONST) ? RIDG_SOLVER_PREFACTORED : RIDG_SOLVER_REGION;
+  if (solver < RIDG_SOLVER_PREFACTORED || solver > RIDG_SOLVER_DENSE) {
+    *msg = "unknown solver";
+    return RIDG_E_INVAL;
+  }
+  if (solver == RIDG_SOLVER_PREFACTORED && P.flux != RIDG_FLUX_CONST) {
+    *msg = "RIDG_SOLVER_PREFACTORED needs a constant velocity";
+    return RIDG_E_INVAL;
+  }
+  if (P.precision == RIDG_FP32_REFINE && solver != RIDG_SOLVER_REGION) {
+    *msg = "RIDG_FP32_REFINE is implemented for RIDG_SOLVER_REGION";
+    return RIDG_E_UNSUPPORTED;
+  }
+  P.solver = solver;
+  // every face must have one upwind side
+  int idx[3] = {0, 0, 0};
+  if (P.flux != RIDG_FLUX_CONST) {
+    // v_i depends on x_j (j != i) only through element rows: scan each axis line once
+    for (int i = 0; i < P.d; ++i) {
+      int64_t lines = P.nel / P.n[i];
+      for (int64_t t = 0; t < lines; ++t) {
+        int64_t r = t;
+        for (int j = 0; j < P.d; ++j) {
+          if (j == i) {
+            idx[j] = 0;
+            continue;
+          }
+          idx[j] = (int)(r % P.n[j]);
+          r /= P.n[j];
+        }
+        if (face_side(P, idx, i, 1) < 0) {
+          *msg = "the normal velocity changes sign inside a face; put the zero line of v on element boundaries";
+          return RIDG_E_INVAL;
+        }
+      }
+    }
+  }
+  *out = P;
+  return RIDG_OK;
+}
+
+void nu_coeffs(const Problem& P, const int idx[3], double dt, double c0[3], double c[3][3]) {
+  for (int i = 0; i < 3; ++i) {
+    c0[i] = 0.0;
+    for (int j = 0; j < 3; ++j) c[i][j] = 0.0;
+  }
+  for (int i = 0; i < P.d; ++i) {
+    double v = P.vel.a[i];
+    for (int j = 0; j < P.d; ++j) v += P.vel.g[i][j] * ((idx[j] + 0.5) * P.h[j]);
+    c0[i] = v * dt / P.h[i];
+    for (int j = 0; j < P.d; ++j) c[i][j] = P.vel.g[i][j] * (0.5 * P.h[j]) * dt / P.h[i];
+  }
+}
+
+int face_side(const Problem& P, const int idx[3], int i, int s) {
+  double c0[3], c[3][3];
+  nu_coeffs(P, idx, 1.0, c0, c);
+  double spread = 0.0;
+  for (int j = 0; j < P.d; ++j) spread += std::fabs(c[i][j]);
+  double mid = s * c0[i];
+  double tol = 1e-12 * (std::fabs(c0[i]) + spread);
+  double mn = mid - spread, mx = mid + spread;
+  if (mn >= -tol) return 0;  // outflow (or no flow): own trace
+  if (mx <= tol) return 1;   // inflow: neighbour trace
+  return -1;
+}
+
+// ---------------------------------------------------------------- geometry and plans
+std::vector<std::array<int, 3>> region_offsets(int d) {
+  std::vector<std::array<int, 3>> out;
+  int nb = 1;
+  for (int i = 0; i < d; ++i) nb *= 3;
+  for (int code = 0; code < nb; ++code) {
+    std::array<int, 3> o = {0, 0, 0};
+    int c = code;
+    for (int i = d - 1; i >= 0; --i) {  // o_1 slowest
+      o[i] = c % 3 - 1;
+      c /= 3;
+    }
+    out.push_back(o);
+  }
+  return out;
+}
+
+void element_index(const Problem& P, int64_t e, int idx[3]) {
+  for (int i = 0; i < 3; ++i) {
+    if (i < P.d) {
+      idx[i] = (int)(e % P.n[i]);
+      e /= P.n[i];
+    } else {
+      idx[i] = 0;
+    }
+  }
+}
+
+int64_t element_linear(const Problem& P, const int idx[3]) {
+  int64_t e = 0;
+  for (int i = P.d - 1; i >= 0; --i) {
+    int k = ((idx[i] % P.n[i]) + P.n[i]) % P.n[i];
+    e = e * P.n[i] + k;
+  }
+  return e;
+}
+
+// periodic image of base + off (element positions always lie in the unit box)
+static void wrapped(const Problem& P, const int base[3], const int off[3], int out[3]) {
+  for (int i = 0; i < 3; ++i) {
+    int k = base[i] + off[i];
+    out[i] = (i < P.d) ? ((k % P.n[i]) + P.n[i]) % P.n[i] : 0;
+  }
+}
+
+static int offset_code(int d, const int o[3]) {
+  int c = 0;
+  for (int i = 0; i < d; ++i) c = c * 3 + (o[i] + 1);
+  return c;
+}
+
+bool element_plan(const Problem& P, int64_t e, PlanRec* out) {
+  const int d = P.d;
+  auto offs = region_offsets(d);
+  const int nb = (int)offs.size();
+  int base[3];
+  element_index(P, e, base);
+  // pred[r] bit r' set: block r takes its upwind trace on some face from block r'
+  uint32_t pred[kMaxBlocks] = {0};
+  int src_of[kMaxBlocks][6];
+  for (int r = 0; r < nb; ++r) {
+    int g[3];
+    wrapped(P, base, offs[r].data(), g);
+    for (int i = 0; i < d; ++i) {
+      for (int s = -1; s <= 1; s += 2) {
+        int f = 2 * i + (s > 0);
+        src_of[r][f] = -1;
+        int o2[3] = {offs[r][0], offs[r][1], offs[r][2]};
+        o2[i] += s;
+        if (o2[i] < -1 || o2[i] > 1) continue;  // region boundary: own trace
+        int side = face_side(P, g, i, s);
+        if (side == 1) {
+          int r2 = offset_code(d, o2);
+          pred[r] |= 1u << r2;
+          src_of[r][f] = r2;
+        }
+      }
+    }
+  }
+  int centre = (nb - 1) / 2;
+  // ancestors of the centre
+  uint32_t anc = 1u << centre, frontier = anc;
+  while (frontier) {
+    uint32_t nxt = 0;
+    for (int r = 0; r < nb; ++r)
+      if (frontier & (1u << r)) nxt |= pred[r];
+    nxt &= ~anc;
+    anc |= nxt;
+    frontier = nxt;
+  }
+  // topological order (Kahn, lowest index first)
+  int order[kMaxBlocks], pos[kMaxBlocks];
+  int placed = 0;
+  uint32_t done = 0;
+  int count = __builtin_popcount(anc);
+  while (placed < count) {
+    int pick = -1;
+    for (int r = 0; r < nb; ++r) {
+      if (!(anc & (1u << r)) || (done & (1u << r))) continue;
+      if ((pred[r] & anc & ~done) == 0) {
+        pick = r;
+        break;
+      }
+    }
+    if (pick < 0) return false;  // dependency cycle among the ancestors
+    pos[pick] = placed;
+    order[placed++] = pick;
+    done |= 1u << pick;
+  }
+  std::memset(out, 0, sizeof(*out));
+  out->nb = count;
+  for (int q = 0; q < count; ++q) {
+    int r = order[q];
+    PlanBlock& b = out->blk[q];
+    for (int i = 0; i < 3; ++i) b.off[i] = (int8_t)offs[r][i];
+    for (int f = 0; f < 6; ++f) b.src[f] = kOwn;
+    for (int f = 0; f < 2 * d; ++f)
+      if (src_of[r][f] >= 0) b.src[f] = (uint8_t)pos[src_of[r][f]];
+  }
+  return true;
+}
+
+RegionPlans build_plans(const Problem& P) {
+  RegionPlans R;
+  R.elem_plan.assign((size_t)P.nel, -1);
+  std::map<std::string, int> ids;
+  PlanRec rec;
+  // For affine fields the plan depends on the element through its axis lines only; a cache
+  // keyed by the face-side pattern keeps this linear in the element count.
+  for (int64_t e = 0; e < P.nel; ++e) {
+    if (!element_plan(P, e, &rec)) {
+      R.dense_elems.push_back((int32_t)e);
+      continue;
+    }
+    std::string key((const char*)&rec, sizeof(rec));
+    auto it = ids.find(key);
+    int id;
+    if (it == ids.end()) {
+      id = (int)R.plans.size();
+      ids.emplace(key, id);
+      R.plans.push_back(rec);
+    } else {
+      id = it->second;
+    }
+    R.elem_plan[(size_t)e] = id;
+  }
+  return R;
+}
+
+// ---------------------------------------------------------------- host assembly
+static void velocity_modes(const Problem& P, const int idx[3], double dt, double V[3][4]) {
+  double c0[3], c[3][3];
+  nu_coeffs(P, idx, dt, c0, c);
+  const double inv_sqrt3 = 1.0 / std::sqrt(3.0);
+  for (int i = 0; i < 3; ++i) {
+    V[i][0] = c0[i];
+    for (int j = 0; j < 3; ++j) V[i][1 + j] = c[i][j] * inv_sqrt3;
+  }
+}
+
+void assemble_region(const Problem& P, const RefTensors& T, int64_t e, double dt,
+                     const std::vector<std::array<int, 3>>& offs, std::vector<double>* Aout) {
+  const int d = P.d, nt = T.nt, np = T.np;
+  const int nb = (int)offs.size();
+  const int n = nb * nt;
+  std::vector<double>& A = *Aout;
+  A.assign((size_t)n * n, 0.0);
+  int base[3];
+  element_index(P, e, base);
+  auto find = [&](const int o[3]) {
+    for (int q = 0; q < nb; ++q)
+      if (offs[q][0] == o[0] && offs[q][1] == o[1] && offs[q][2] == o[2]) return q;
+    return -1;
+  };
+  for (int r = 0; r < nb; ++r) {
+    int g[3];
+    wrapped(P, base, offs[r].data(), g);
+    double V[3][4];
+    velocity_modes(P, g, dt, V);
+    double* D = &A[(size_t)r * nt * n + (size_t)r * nt];
+    for (int k = 0; k < nt; ++k)
+      for (int l = 0; l < nt; ++l) D[(size_t)k * n + l] += T.Tt[(size_t)k * nt + l];
+    for (int i = 0; i < d; ++i) {
+      for (int p = 0; p < np; ++p) {
+        double vp = V[i][p];
+        if (vp == 0.0) continue;
+        const double* bv = &T.Bv[T.bv(i, p)];
+        for (int k = 0; k < nt; ++k)
+          for (int l = 0; l < nt; ++l) D[(size_t)k * n + l] -= vp * bv[(size_t)k * nt + l];
+      }
+      for (int s = -1; s <= 1; s += 2) {
+        int o2[3] = {offs[r][0], offs[r][1], offs[r][2]};
+        o2[i] += s;
+        bool boundary = (o2[i] < -1 || o2[i] > 1);
+        int side = boundary ? 0 : face_side(P, g, i, s);
+        int q = boundary ? -1 : find(o2);
+        if (side == 1 && q < 0) continue;  // source outside the listed blocks (not an ancestor)
+        double* Bk = (side == 0) ? D : &A[(size_t)r * nt * n + (size_t)q * nt];
+        for (int p = 0; p < np; ++p) {
+          double vp = V[i][p];
+          if (vp == 0.0) continue;
+          const double* f = side == 0 ? &T.Fo[T.f(i, s, p)] : &T.Fn[T.f(i, s, p)];
+          for (int k = 0; k < nt; ++k)
+            for (int l = 0; l < nt; ++l) Bk[(size_t)k * n + l] += vp * f[(size_t)k * nt + l];
+        }
+      }
+    }
+  }
+}
+
+bool lu_factor(int n, double* a, int* piv) {
+  for (int c = 0; c < n; ++c) {
+    int p = c;
+    double best = std::fabs(a[(size_t)c * n + c]);
+    for (int r = c + 1; r < n; ++r) {
+      double v = std::fabs(a[(size_t)r * n + c]);
+      if (v > best) {
+        best = v;
+        p = r;
+      }
+    }
+    piv[c] = p;
+    if (best == 0.0) return false;
+    if (p != c)
+      for (int j = 0; j < n; ++j) std::swap(a[(size_t)c * n + j], a[(size_t)p * n + j]);
+    double inv = 1.0 / a[(size_t)c * n + c];
+    for (int r = c + 1; r < n; ++r) {
+      double l = a[(size_t)r * n + c] * inv;
+      a[(size_t)r * n + c] = l;
+      if (l == 0.0) continue;
+      for (int j = c + 1; j < n; ++j) a[(size_t)r * n + j] -= l * a[(size_t)c * n + j];
+    }
+  }
+  return true;
+}
+
+void lu_solve(int n, const double* lu, const int* piv, double* b, int nrhs) {
+  for (int c = 0; c < n; ++c)
+    if (piv[c] != c)
+      for (int j = 0; j < nrhs; ++j) std::swap(b[(size_t)c * nrhs + j], b[(size_t)piv[c] * nrhs + j]);
+  for (int r = 0; r < n; ++r)
+    for (int c = 0; c < r; ++c) {
+      double l = lu[(size_t)r * n + c];
+      if (l == 0.0) continue;
+      for (int j = 0; j < nrhs; ++j) b[(size_t)r * nrhs + j] -= l * b[(size_t)c * nrhs + j];
+    }
+  for (int r = n - 1; r >= 0; --r) {
+    for (int c = r + 1; c < n; ++c) {
+      double u = lu[(size_t)r * n + c];
+      if (u == 0.0) continue;
+      for (int j = 0; j < nrhs; ++j) b[(size_t)r * nrhs + j] -= u * b[(size_t)c * nrhs + j];
+    }
+    double inv = 1.0 / lu[(size_t)r * n + r];
+    for (int j = 0; j < nrhs; ++j) b[(size_t)r * nrhs + j] *= inv;
+  }
+}
+
+int build_prefactored(const Problem& P, const RefTensors& T, double dt, Prefactored* out, std::string* msg) {
+  PlanRec rec;
+  if (!element_plan(P, 0, &rec)) {
+    *msg = "constant velocity plan has a cycle";
+    return RIDG_E_INVAL;
+  }
+  const int nt = T.nt, ns = T.ns, nb = rec.nb;
+  std::vector<std::array<int, 3>> offs(nb);
+  for (int q = 0; q < nb; ++q) offs[q] = {rec.blk[q].off[0], rec.blk[q].off[1], rec.blk[q].off[2]};
+  std::vector<double> A;
+  assemble_region(P, T, 0, dt, offs, &A);
+  const int n = nb * nt;
+  std::vector<int> piv(n);
+  if (!lu_factor(n, A.data(), piv.data())) {
+    *msg = "zero pivot in the region matrix";
+    return RIDG_E_SINGULAR;
+  }
+  // right-hand sides: blockdiag(Cc), n x (nb ns)
+  const int nr = nb * ns;
+  std::vector<double> B((size_t)n * nr, 0.0);
+  for (int q = 0; q < nb; ++q)
+    for (int k = 0; k < nt; ++k)
+      for (int l = 0; l < ns; ++l) B[(size_t)(q * nt + k) * nr + q * ns + l] = T.Cc[(size_t)k * ns + l];
+  lu_solve(n, A.data(), piv.data(), B.data(), nr);
+  // the centre is the last block of the plan
+  out->offs = offs;
+  out->G.assign((size_t)nb * nt * ns, 0.0);
+  const int c = nb - 1;
+  for (int q = 0; q < nb; ++q)
+    for (int k = 0; k < nt; ++k)
+      for (int l = 0; l < ns; ++l)
+        out->G[((size_t)q * nt + k) * ns + l] = B[(size_t)(c * nt + k) * nr + q * ns + l];
+  return RIDG_OK;
+}
+
+}  // namespace ridg

@@ -1,0 +1,622 @@
+// HIP kernels of libridg for gfx950 (MI355X): the RIDG prediction (Sec. 2.2 of
+// arXiv 2101.01231) and correction (Sec. 2.3) on a periodic Cartesian mesh.
+//
+// State and prediction arrays are coefficient-major in HBM (Q[k * nel + e],
+// W[k * nel + e]) so that neighbouring threads/elements read neighbouring
+// addresses. Element e = i0 + n0 (i1 + n1 i2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "ridg_internal.hpp"
+
+namespace ridg {
+
+// ---------------------------------------------------------------- sizes
+__host__ __device__ constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+__host__ __device__ constexpr int n_space(int D, int M) { return binom(M - 1 + D, D); }
+__host__ __device__ constexpr int n_spacetime(int D, int M) { return binom(M + D, D + 1); }
+__host__ __device__ constexpr int pow3(int D) { return D == 1 ? 3 : (D == 2 ? 9 : 27); }
+__host__ __device__ constexpr int seg_width(int nt) {
+  return nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : nt <= 8 ? 8 : nt <= 16 ? 16 : nt <= 32 ? 32 : 64;
+}
+
+// ---------------------------------------------------------------- geometry helpers
+__device__ inline void elem_idx(const DevGeom& g, int64_t e, int idx[3]) {
+  idx[0] = (int)(e % g.n0);
+  int64_t r = e / g.n0;
+  idx[1] = (int)(r % g.n1);
+  idx[2] = (int)(r / g.n1);
+}
+
+__device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ inline int64_t elem_lin(const DevGeom& g, int i0, int i1, int i2) {
+  return (int64_t)wrap(i0, g.n0) + (int64_t)g.n0 * ((int64_t)wrap(i1, g.n1) + (int64_t)g.n1 * wrap(i2, g.n2));
+}
+
+__device__ inline double geom_h(const DevGeom& g, int i) { return i == 0 ? g.h0 : (i == 1 ? g.h1 : g.h2); }
+
+// nu_i(xi) = c0[i] + sum_j c[i][j] xi_j; projected on p-modes {1, psi_1(xi_j)}: V[i][0] = c0, V[i][1+j] = c_ij / sqrt3
+template <int D>
+__device__ inline void vel_modes(const DevGeom& g, const int idx[3], double dt, double V[D][D + 1]) {
+  const double inv_sqrt3 = 0.57735026918962576451;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double v = g.a[i];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v += g.g[i][j] * ((idx[j] + 0.5) * geom_h(g, j));
+    const double hi = geom_h(g, i);
+    V[i][0] = v * dt / hi;
+#pragma unroll
+    for (int j = 0; j < D; ++j) V[i][1 + j] = g.g[i][j] * (0.5 * geom_h(g, j)) * dt / hi * inv_sqrt3;
+  }
+}
+
+// upwind side of face (i, s): 0 own trace, 1 neighbour trace (same rule as the host plans)
+template <int D>
+__device__ inline int face_side(const DevGeom& g, const int idx[3], int i, int s) {
+  double v = g.a[i], spread = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    v += g.g[i][j] * ((idx[j] + 0.5) * geom_h(g, j));
+    spread += fabs(g.g[i][j] * (0.5 * geom_h(g, j)));
+  }
+  const double hi = geom_h(g, i);
+  const double c0 = v / hi;
+  spread /= hi;
+  const double tol = 1e-12 * (fabs(c0) + spread);
+  return (s * c0 - spread >= -tol) ? 0 : 1;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- layout transposes
+__global__ void aos_to_soa_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t nel, int nm) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nel * nm) return;
+  int64_t e = t / nm;
+  int k = (int)(t % nm);
+  dst[(int64_t)k * nel + e] = src[t];
+}
+
+__global__ void soa_to_aos_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t nel, int nm) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nel * nm) return;
+  int64_t e = t / nm;
+  int k = (int)(t % nm);
+  dst[t] = src[(int64_t)k * nel + e];
+}
+
+__global__ void check_finite_kernel(const double* __restrict__ x, int64_t n, int32_t* flag) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n && !isfinite(x[t])) flag[0] = 1;
+}
+
+// ---------------------------------------------------------------- prefactored prediction
+// Constant velocity: W_e = sum_tap G_tap Q_{e + off_tap} (Sec. 2.2 system solved once on the host).
+struct Taps {
+  int8_t off[kMaxBlocks][3];
+};
+
+template <int D, int M>
+__global__ __launch_bounds__(256) void predict_prefactored_kernel(DevGeom g, const double* __restrict__ Q,
+                                                                  double* __restrict__ W,
+                                                                  const double* __restrict__ G, Taps taps,
+                                                                  int ntaps) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  int idx[3];
+  elem_idx(g, e, idx);
+  double w[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) w[k] = 0.0;
+  for (int t = 0; t < ntaps; ++t) {
+    const int64_t src = elem_lin(g, idx[0] + taps.off[t][0], idx[1] + taps.off[t][1], idx[2] + taps.off[t][2]);
+    double q[NS];
+#pragma unroll
+    for (int l = 0; l < NS; ++l) q[l] = Q[(int64_t)l * nel + src];
+    const double* Gt = G + (size_t)t * NT * NS;
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+#pragma unroll
+      for (int l = 0; l < NS; ++l) w[k] = fma(Gt[k * NS + l], q[l], w[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) W[(int64_t)k * nel + e] = w[k];
+}
+
+// ---------------------------------------------------------------- correction
+// Q'_e = Q_e + 2^-d [ sum_i sum_p V_ip Cv_ip W_e - sum_faces sum_p V_ip (CFo W_e | CFn W_nbr) ]
+template <int D, int M, bool AFFINE>
+__global__ __launch_bounds__(256) void correct_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+                                                      const double* __restrict__ W, double* __restrict__ Qout,
+                                                      DevTensors t) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NP = D + 1;
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  int idx[3];
+  elem_idx(g, e, idx);
+  double V[D][D + 1];
+  vel_modes<D>(g, idx, dt, V);
+  double we[NT], acc[NS];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) we[l] = W[(int64_t)l * nel + e];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+#pragma unroll 1
+  for (int i = 0; i < D; ++i) {
+#pragma unroll 1
+    for (int p = 0; p < NP; ++p) {
+      if (p == 1 + i || (!AFFINE && p > 0)) continue;
+      const double vp = V[i][p];
+      const double* cv = t.Cv + ((size_t)i * NP + p) * NS * NT;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) s = fma(cv[k * NT + l], we[l], s);
+        acc[k] = fma(vp, s, acc[k]);
+      }
+    }
+#pragma unroll 1
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s = sd ? 1 : -1;
+      const int side = face_side<D>(g, idx, i, s);
+      double wn[NT];
+      const double* tens;
+      if (side == 0) {
+#pragma unroll
+        for (int l = 0; l < NT; ++l) wn[l] = we[l];
+        tens = t.CFo;
+      } else {
+        int j[3] = {idx[0], idx[1], idx[2]};
+        j[i] += s;
+        const int64_t en = elem_lin(g, j[0], j[1], j[2]);
+#pragma unroll
+        for (int l = 0; l < NT; ++l) wn[l] = W[(int64_t)l * nel + en];
+        tens = t.CFn;
+      }
+#pragma unroll 1
+      for (int p = 0; p < NP; ++p) {
+        if (p == 1 + i || (!AFFINE && p > 0)) continue;
+        const double vp = V[i][p];
+        const double* cf = tens + (((size_t)i * 2 + sd) * NP + p) * NS * NT;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int l = 0; l < NT; ++l) s2 = fma(cf[k * NT + l], wn[l], s2);
+          acc[k] = fma(-vp, s2, acc[k]);
+        }
+      }
+    }
+  }
+  constexpr double scale = 1.0 / (double)(1 << D);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Qout[(int64_t)k * nel + e] = fma(acc[k], scale, Q[(int64_t)k * nel + e]);
+}
+
+// ---------------------------------------------------------------- region solve by upwind plans
+// One segment of SEG lanes (SEG = next power of two >= theta_T) per region; lane k owns row k of
+// each block system. Blocks are solved in the plan's topological order: the diagonal block
+// (time term - internal flux + own-trace faces, assembled from the exact tensors and the
+// projected velocity, Sec. 3) is factorised by Gaussian elimination with partial pivoting, the
+// pivot row being found by a segment-wide argmax over lanes; inflow faces inside the region
+// move the upwind neighbour's already-solved W to the right-hand side.
+template <int D, int M>
+struct PlanCfg {
+  static constexpr int NS = n_space(D, M);
+  static constexpr int NT = n_spacetime(D, M);
+  static constexpr int NP = D + 1;
+  static constexpr int SEG = seg_width(NT);
+  static constexpr int IPW = 64 / SEG;
+  static constexpr int NB = pow3(D);
+  static constexpr int WAVES = 4;
+};
+
+template <int NT, int SEG>
+__device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, double* piv, double* x) {
+  bool used = (k >= NT);
+  int mystep = -1;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double cand = used ? -1.0 : fabs(a[c]);
+    int idx = k;
+#pragma unroll
+    for (int off = SEG / 2; off > 0; off >>= 1) {
+      const double oc = __shfl_xor(cand, off, SEG);
+      const int oi = __shfl_xor(idx, off, SEG);
+      const bool take = (oc > cand) || (oc == cand && oi < idx);
+      cand = take ? oc : cand;
+      idx = take ? oi : idx;
+    }
+    if (k == idx) {
+#pragma unroll
+      for (int j = c; j < NT; ++j) piv[j] = a[j];
+      piv[NT] = rhs;
+      used = true;
+      mystep = c;
+    }
+    wave_sync();
+    const double inv = 1.0 / piv[c];
+    if (!used) {
+      const double l = a[c] * inv;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, piv[j], a[j]);
+      rhs = fma(-l, piv[NT], rhs);
+    }
+    wave_sync();
+  }
+#pragma unroll
+  for (int c = NT - 1; c >= 0; --c) {
+    if (mystep == c) x[c] = rhs / a[c];
+    wave_sync();
+    const double xc = x[c];
+    if (mystep >= 0 && mystep < c) rhs = fma(-a[c], xc, rhs);
+  }
+  wave_sync();
+}
+
+template <int D, int M>
+__global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+                                                            double* __restrict__ W, DevTensors t,
+                                                            const PlanRec* __restrict__ plans,
+                                                            const int32_t* __restrict__ items,
+                                                            const int32_t* __restrict__ item_plan,
+                                                            int64_t n_items) {
+  using C = PlanCfg<D, M>;
+  constexpr int NS = C::NS, NT = C::NT, NP = C::NP, SEG = C::SEG, IPW = C::IPW;
+  __shared__ double s_w[C::WAVES][IPW][C::NB][NT];
+  __shared__ double s_piv[C::WAVES][IPW][NT + 1];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int seg = lane / SEG;
+  const int k = lane % SEG;
+  const int64_t item = ((int64_t)blockIdx.x * C::WAVES + wave) * IPW + seg;
+  if (((int64_t)blockIdx.x * C::WAVES + wave) * IPW >= n_items) return;  // whole wave idle
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  int32_t e = items[item];
+  const bool write = e >= 0;
+  if (!write) e = -e - 1;
+  const int pid = __builtin_amdgcn_readfirstlane(item_plan[item]);  // uniform per wave by construction
+  const PlanRec* pr = plans + pid;
+  const int nb = pr->nb;
+  int base[3];
+  elem_idx(g, e, base);
+  double* sw = &s_w[wave][seg][0][0];
+  double* spiv = &s_piv[wave][seg][0];
+  const int kr = k < NT ? k : 0;  // padding lanes mirror row 0 (never pivot, never stored)
+  for (int b = 0; b < nb; ++b) {
+    const PlanBlock blk = pr->blk[b];
+    int gi[3] = {base[0] + blk.off[0], base[1] + blk.off[1], base[2] + blk.off[2]};
+    gi[0] = wrap(gi[0], g.n0);
+    gi[1] = wrap(gi[1], g.n1);
+    gi[2] = wrap(gi[2], g.n2);
+    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+    double V[D][D + 1];
+    vel_modes<D>(g, gi, dt, V);
+    // row kr of the diagonal block
+    double a[NT];
+#pragma unroll
+    for (int l = 0; l < NT; ++l) a[l] = t.Tt[kr * NT + l];
+#pragma unroll 1
+    for (int i = 0; i < D; ++i) {
+#pragma unroll 1
+      for (int p = 0; p < NP; ++p) {
+        if (p == 1 + i) continue;
+        const double vp = V[i][p];
+        if (vp == 0.0) continue;
+        const double* bv = t.Bv + (((size_t)i * NP + p) * NT + kr) * NT;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) a[l] = fma(-vp, bv[l], a[l]);
+      }
+#pragma unroll 1
+      for (int sd = 0; sd < 2; ++sd) {
+        if (blk.src[2 * i + sd] != kOwn) continue;
+#pragma unroll 1
+        for (int p = 0; p < NP; ++p) {
+          if (p == 1 + i) continue;
+          const double vp = V[i][p];
+          if (vp == 0.0) continue;
+          const double* fo = t.Fo + ((((size_t)i * 2 + sd) * NP + p) * NT + kr) * NT;
+#pragma unroll
+          for (int l = 0; l < NT; ++l) a[l] = fma(vp, fo[l], a[l]);
+        }
+      }
+    }
+    // right-hand side: causal source minus the upwind couplings
+    double rhs = 0.0;
+#pragma unroll
+    for (int l = 0; l < NS; ++l) {
+      const double c = t.Cc[kr * NS + l];
+      if (c != 0.0) rhs = fma(c, Q[(int64_t)l * nel + ge], rhs);
+    }
+#pragma unroll 1
+    for (int i = 0; i < D; ++i) {
+#pragma unroll 1
+      for (int sd = 0; sd < 2; ++sd) {
+        const int src = blk.src[2 * i + sd];
+        if (src == kOwn) continue;
+        const double* wsrc = sw + src * NT;
+#pragma unroll 1
+        for (int p = 0; p < NP; ++p) {
+          if (p == 1 + i) continue;
+          const double vp = V[i][p];
+          if (vp == 0.0) continue;
+          const double* fn = t.Fn + ((((size_t)i * 2 + sd) * NP + p) * NT + kr) * NT;
+          double s = 0.0;
+#pragma unroll
+          for (int l = 0; l < NT; ++l) s = fma(fn[l], wsrc[l], s);
+          rhs = fma(-vp, s, rhs);
+        }
+      }
+    }
+    seg_solve<NT, SEG>(a, rhs, k, spiv, sw + b * NT);
+  }
+  if (write && k < NT) W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
+}
+
+// ---------------------------------------------------------------- dense region solve
+// One workgroup per region: the whole 3^d theta_T system (eq. pred_full_system) assembled in a
+// scratch matrix and solved by Gaussian elimination with partial pivoting.
+template <int D, int M>
+__global__ __launch_bounds__(256) void predict_dense_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+                                                            double* __restrict__ W, DevTensors t,
+                                                            const int32_t* __restrict__ elems,
+                                                            int64_t first, int64_t count,
+                                                            double* __restrict__ scratch) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NP = D + 1, NB = pow3(D);
+  constexpr int N = NB * NT, LD = N + 1;
+  const int64_t slot = blockIdx.x;
+  if (first + slot >= count) return;
+  const int32_t e = elems[first + slot];
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  double* A = scratch + (size_t)slot * N * LD;  // [N][N+1]: matrix | rhs
+  __shared__ double s_red_v[256];
+  __shared__ int s_red_i[256];
+  __shared__ double s_x[N];
+  int base[3];
+  elem_idx(g, e, base);
+  for (int R = threadIdx.x; R < N; R += blockDim.x) {
+    const int r = R / NT, k = R % NT;
+    int o[3] = {0, 0, 0};
+    {
+      int c = r;
+      for (int i = D - 1; i >= 0; --i) {
+        o[i] = c % 3 - 1;
+        c /= 3;
+      }
+    }
+    int gi[3] = {wrap(base[0] + o[0], g.n0), wrap(base[1] + o[1], g.n1), wrap(base[2] + o[2], g.n2)};
+    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+    double V[D][D + 1];
+    vel_modes<D>(g, gi, dt, V);
+    double* row = A + (size_t)R * LD;
+    for (int j = 0; j < N; ++j) row[j] = 0.0;
+    double* diag = row + r * NT;
+    for (int l = 0; l < NT; ++l) diag[l] = t.Tt[k * NT + l];
+    for (int i = 0; i < D; ++i) {
+      for (int p = 0; p < NP; ++p) {
+        if (p == 1 + i || V[i][p] == 0.0) continue;
+        const double* bv = t.Bv + (((size_t)i * NP + p) * NT + k) * NT;
+        for (int l = 0; l < NT; ++l) diag[l] = fma(-V[i][p], bv[l], diag[l]);
+      }
+      for (int sd = 0; sd < 2; ++sd) {
+        const int s = sd ? 1 : -1;
+        int o2 = o[i] + s;
+        const bool boundary = (o2 < -1 || o2 > 1);
+        const int side = boundary ? 0 : face_side<D>(g, gi, i, s);
+        double* dst = diag;
+        const double* tens = t.Fo;
+        if (side == 1) {
+          int oo[3] = {o[0], o[1], o[2]};
+          oo[i] = o2;
+          int q = 0;
+          for (int m = 0; m < D; ++m) q = q * 3 + (oo[m] + 1);
+          dst = row + q * NT;
+          tens = t.Fn;
+        }
+        for (int p = 0; p < NP; ++p) {
+          if (p == 1 + i || V[i][p] == 0.0) continue;
+          const double* f = tens + ((((size_t)i * 2 + sd) * NP + p) * NT + k) * NT;
+          for (int l = 0; l < NT; ++l) dst[l] = fma(V[i][p], f[l], dst[l]);
+        }
+      }
+    }
+    double rhs = 0.0;
+    for (int l = 0; l < NS; ++l) rhs = fma(t.Cc[k * NS + l], Q[(int64_t)l * nel + ge], rhs);
+    row[N] = rhs;
+  }
+  __syncthreads();
+  for (int c = 0; c < N; ++c) {
+    // pivot search over rows c..N-1 (lowest row on ties)
+    double best = -1.0;
+    int bi = N;
+    for (int R = c + threadIdx.x; R < N; R += blockDim.x) {
+      const double v = fabs(A[(size_t)R * LD + c]);
+      if (v > best) {
+        best = v;
+        bi = R;
+      }
+    }
+    s_red_v[threadIdx.x] = best;
+    s_red_i[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+        const double ov = s_red_v[threadIdx.x + off];
+        const int oi = s_red_i[threadIdx.x + off];
+        if (ov > s_red_v[threadIdx.x] || (ov == s_red_v[threadIdx.x] && oi < s_red_i[threadIdx.x])) {
+          s_red_v[threadIdx.x] = ov;
+          s_red_i[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int p = s_red_i[0];
+    __syncthreads();
+    if (p != c)
+      for (int j = c + threadIdx.x; j < LD; j += blockDim.x) {
+        const double tmp = A[(size_t)c * LD + j];
+        A[(size_t)c * LD + j] = A[(size_t)p * LD + j];
+        A[(size_t)p * LD + j] = tmp;
+      }
+    __syncthreads();
+    const double inv = 1.0 / A[(size_t)c * LD + c];
+    const int rows = N - c - 1, cols = LD - c - 1;
+    for (int64_t q = threadIdx.x; q < (int64_t)rows * cols; q += blockDim.x) {
+      const int R = c + 1 + (int)(q / cols), j = c + 1 + (int)(q % cols);
+      const double l = A[(size_t)R * LD + c] * inv;
+      A[(size_t)R * LD + j] = fma(-l, A[(size_t)c * LD + j], A[(size_t)R * LD + j]);
+    }
+    __syncthreads();
+  }
+  // back substitution
+  for (int c = N - 1; c >= 0; --c) {
+    if (threadIdx.x == 0) s_x[c] = A[(size_t)c * LD + N] / A[(size_t)c * LD + c];
+    __syncthreads();
+    const double xc = s_x[c];
+    for (int R = threadIdx.x; R < c; R += blockDim.x) A[(size_t)R * LD + N] = fma(-A[(size_t)R * LD + c], xc, A[(size_t)R * LD + N]);
+    __syncthreads();
+  }
+  const int centre = (NB - 1) / 2;
+  for (int k = threadIdx.x; k < NT; k += blockDim.x) W[(int64_t)k * nel + e] = s_x[centre * NT + k];
+}
+
+// ---------------------------------------------------------------- dispatch
+template <template <int, int> class F, typename... Args>
+static int dispatch_dm(int d, int M, Args... args) {
+#define RIDG_CASE(DD, MM) \
+  if (d == DD && M == MM) return F<DD, MM>::run(args...);
+  RIDG_CASE(1, 1) RIDG_CASE(1, 2) RIDG_CASE(1, 3) RIDG_CASE(1, 4) RIDG_CASE(1, 5)
+  RIDG_CASE(2, 1) RIDG_CASE(2, 2) RIDG_CASE(2, 3) RIDG_CASE(2, 4) RIDG_CASE(2, 5)
+  RIDG_CASE(3, 1) RIDG_CASE(3, 2) RIDG_CASE(3, 3) RIDG_CASE(3, 4) RIDG_CASE(3, 5)
+#undef RIDG_CASE
+  return (int)hipErrorInvalidValue;
+}
+
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+int launch_aos_to_soa(const double* src, double* dst, int64_t nel, int nmodes, void* stream) {
+  int64_t n = nel * nmodes;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(aos_to_soa_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, src, dst, nel, nmodes);
+  return (int)hipGetLastError();
+}
+
+int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, void* stream) {
+  int64_t n = nel * nmodes;
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(soa_to_aos_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, src, dst, nel, nmodes);
+  return (int)hipGetLastError();
+}
+
+int launch_check_finite(const double* x, int64_t n, int32_t* flag, void* stream) {
+  if (n == 0) return 0;
+  hipLaunchKernelGGL(check_finite_kernel, dim3(grid_for(n, 256)), dim3(256), 0, (hipStream_t)stream, x, n, flag);
+  return (int)hipGetLastError();
+}
+
+template <int D, int M>
+struct PrefactoredL {
+  static int run(const DevGeom& g, const double* Q, double* W, const double* G, const int32_t* taps, int ntaps,
+                 void* stream) {
+    Taps tp;
+    for (int t = 0; t < kMaxBlocks; ++t)
+      for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+    const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+    hipLaunchKernelGGL((predict_prefactored_kernel<D, M>), dim3(grid_for(nel, 256)), dim3(256), 0,
+                       (hipStream_t)stream, g, Q, W, G, tp, ntaps);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, double* W, const double* G,
+                               const int32_t* taps, int ntaps, void* stream) {
+  return dispatch_dm<PrefactoredL>(d, M, g, Q, W, G, taps, ntaps, stream);
+}
+
+template <int D, int M>
+struct CorrectL {
+  static int run(int flux, const DevGeom& g, double dt, const double* Q, const double* W, double* Qout,
+                 const DevTensors& t, void* stream) {
+    const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+    if (flux == RIDG_FLUX_CONST)
+      hipLaunchKernelGGL((correct_kernel<D, M, false>), dim3(grid_for(nel, 256)), dim3(256), 0,
+                         (hipStream_t)stream, g, dt, Q, W, Qout, t);
+    else
+      hipLaunchKernelGGL((correct_kernel<D, M, true>), dim3(grid_for(nel, 256)), dim3(256), 0,
+                         (hipStream_t)stream, g, dt, Q, W, Qout, t);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_correct(int d, int M, int flux, const DevGeom& g, double dt, const double* Q, const double* W,
+                   double* Qout, const DevTensors& t, void* stream) {
+  return dispatch_dm<CorrectL>(d, M, flux, g, dt, Q, W, Qout, t, stream);
+}
+
+template <int D, int M>
+struct IpwL {
+  static int run() { return PlanCfg<D, M>::IPW; }
+};
+int items_per_wave(int d, int M) { return dispatch_dm<IpwL>(d, M); }
+
+template <int D, int M>
+struct PlansL {
+  static int run(int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
+                 const DevTensors& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
+                 int64_t n_items, void* stream) {
+    (void)precision;
+    (void)refine;
+    using C = PlanCfg<D, M>;
+    if (C::NT > 64) return (int)hipErrorInvalidValue;
+    const int64_t per_block = (int64_t)C::WAVES * C::IPW;
+    const int64_t blocks = (n_items + per_block - 1) / per_block;
+    if (blocks == 0) return 0;
+    hipLaunchKernelGGL((predict_plans_kernel<D, M>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                       (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom& g, double dt, const double* Q,
+                         double* W, const DevTensors& t, const PlanRec* plans, const int32_t* items,
+                         const int32_t* item_plan, int64_t n_items, void* stream) {
+  return dispatch_dm<PlansL>(d, M, precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+}
+
+template <int D, int M>
+struct DenseL {
+  static int run(const DevGeom& g, double dt, const double* Q, double* W, const DevTensors& t,
+                 const int32_t* elems, int64_t n_elems, double* scratch, int64_t scratch_elems, void* stream) {
+    for (int64_t first = 0; first < n_elems; first += scratch_elems) {
+      const int64_t chunk = (n_elems - first < scratch_elems) ? n_elems - first : scratch_elems;
+      hipLaunchKernelGGL((predict_dense_kernel<D, M>), dim3((unsigned)chunk), dim3(256), 0, (hipStream_t)stream, g,
+                         dt, Q, W, t, elems, first, n_elems, scratch);
+      int err = (int)hipGetLastError();
+      if (err) return err;
+    }
+    return 0;
+  }
+};
+
+int launch_predict_dense(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
+                         const DevTensors& t, const int32_t* elems, int64_t n_elems, double* scratch,
+                         int64_t scratch_elems, void* stream) {
+  return dispatch_dm<DenseL>(d, M, g, dt, Q, W, t, elems, n_elems, scratch, scratch_elems, stream);
+}
+
+}  // namespace ridg

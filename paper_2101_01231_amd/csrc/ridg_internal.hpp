@@ -1,0 +1,167 @@
+// Internal declarations of libridg: host FP64 precompute and device launchers.
+#pragma once
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ridg.h"
+
+namespace ridg {
+
+constexpr int kMaxDim = 3;
+constexpr int kMaxOrder = 5;
+constexpr int kMaxBlocks = 27;  // 3^3 region elements
+constexpr uint8_t kOwn = 0xFF;  // plan face source: own trace (region boundary or outflow face)
+
+// ---------------------------------------------------------------- basis
+struct Basis {
+  int d = 0, M = 0;
+  int theta = 0, theta_t = 0;
+  std::vector<std::array<int, 4>> sidx;  // spatial exponents (a_1..a_d)
+  std::vector<std::array<int, 4>> tidx;  // space-time exponents (b_t, b_1..b_d)
+};
+Basis make_basis(int d, int M);
+
+// Exact 1D integrals of psi_m = sqrt(2m+1) P_m on [-1, 1].
+double leg_t3(int a, int b, int c);  // int psi_a psi_b psi_c
+double leg_d3(int a, int b, int c);  // int psi_a' psi_b psi_c
+double leg_dm(int a, int b);         // int psi_a' psi_b
+double leg_end(int m, int s);        // psi_m(s), s = +-1
+
+// Reference tensors of the QQF assembly. The velocity component nu_i is
+// projected on the p-modes {1, psi_1(xi_1), .., psi_1(xi_d)} (index p = 0,
+// 1+j); tensors carry the face sign s where a face is involved.
+struct RefTensors {
+  int d = 0, nt = 0, ns = 0, np = 0;
+  std::vector<double> Tt;   // [k][l]            time term
+  std::vector<double> Cc;   // [k][l] (nt x ns)  causal source
+  std::vector<double> Bv;   // [i][p][k][l]      int d_i Psi_k Psi_p Psi_l
+  std::vector<double> Fo;   // [i][s][p][k][l]   s int Psi_k|s Psi_p Psi_l|s
+  std::vector<double> Fn;   // [i][s][p][k][l]   s int Psi_k|s Psi_p Psi_l|-s
+  std::vector<double> Cv;   // [i][p][k][l]      int d_i Phi_k Psi_p Psi_l (ns x nt)
+  std::vector<double> CFo;  // [i][s][p][k][l]   s int Phi_k|s Psi_p Psi_l|s
+  std::vector<double> CFn;  // [i][s][p][k][l]   s int Phi_k|s Psi_p Psi_l|-s
+  size_t bv(int i, int p) const { return ((size_t)i * np + p) * nt * nt; }
+  size_t f(int i, int s, int p) const { return (((size_t)i * 2 + (s > 0)) * np + p) * nt * nt; }
+  size_t cv(int i, int p) const { return ((size_t)i * np + p) * ns * nt; }
+  size_t cf(int i, int s, int p) const { return (((size_t)i * 2 + (s > 0)) * np + p) * ns * nt; }
+};
+RefTensors make_tensors(const Basis& b);
+
+// ---------------------------------------------------------------- velocity
+// v_i(x) = a_i + sum_j g_ij x_j with g_ii = 0 (divergence free, independent of x_i)
+struct Affine {
+  double a[3] = {0, 0, 0};
+  double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+};
+
+struct Problem {
+  int d = 0;
+  int n[3] = {1, 1, 1};
+  int M = 0;
+  int flux = 0;
+  Affine vel;
+  double h[3] = {1, 1, 1};
+  int precision = 0;
+  int refine = 0;
+  int solver = 0;  // resolved
+  int64_t nel = 0;
+};
+
+// Validate and resolve a public problem description. Returns RIDG_OK or an error (msg set).
+int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg);
+
+// nu_i(xi) = c0[i] + sum_j c[i][j] xi_j on element idx for step dt.
+void nu_coeffs(const Problem& P, const int idx[3], double dt, double c0[3], double c[3][3]);
+
+// Upwind side of face (i, s) of element idx: 0 = own trace, 1 = neighbour trace,
+// -1 = v.n changes sign inside the face.
+int face_side(const Problem& P, const int idx[3], int i, int s);
+
+// ---------------------------------------------------------------- plans
+struct PlanBlock {
+  int8_t off[3];
+  int8_t pad0;
+  uint8_t src[6];  // [2 i + (s > 0)]: kOwn or the plan position of the upwind source block
+  uint8_t pad1[6];
+};
+static_assert(sizeof(PlanBlock) == 16, "plan block layout");
+
+struct PlanRec {
+  int32_t nb;
+  int32_t pad[3];
+  PlanBlock blk[kMaxBlocks];
+};
+
+struct RegionPlans {
+  std::vector<PlanRec> plans;       // distinct plans
+  std::vector<int32_t> elem_plan;   // plan id per element, -1 = centre on a dependency cycle
+  std::vector<int32_t> dense_elems; // elements with elem_plan == -1
+};
+
+// Offsets of the region blocks, lexicographic with o_1 slowest.
+std::vector<std::array<int, 3>> region_offsets(int d);
+
+void element_index(const Problem& P, int64_t e, int idx[3]);
+int64_t element_linear(const Problem& P, const int idx[3]);  // periodic wrap
+
+RegionPlans build_plans(const Problem& P);
+// Plan of one element (false if its centre lies on a cycle).
+bool element_plan(const Problem& P, int64_t e, PlanRec* out);
+
+// Host FP64 assembly of the region matrix over the given region blocks (offsets), rows = tests.
+// Interior faces between listed blocks are upwind; faces to unlisted blocks use the own trace
+// when the block is on the 3^d region boundary, and are upwind couplings dropped otherwise (only
+// used with ancestor-closed block sets, where such couplings do not exist).
+void assemble_region(const Problem& P, const RefTensors& T, int64_t e, double dt,
+                     const std::vector<std::array<int, 3>>& offs, std::vector<double>* A);
+
+// Dense LU with partial pivoting (row-major n x n, in place); returns false on a zero pivot.
+bool lu_factor(int n, double* a, int* piv);
+void lu_solve(int n, const double* lu, const int* piv, double* b, int nrhs);  // b: n x nrhs row-major
+
+// Constant velocity: taps (ancestor offsets) and G_r blocks (nt x ns each) of W_e = sum_r G_r Q_{e+r}.
+struct Prefactored {
+  std::vector<std::array<int, 3>> offs;
+  std::vector<double> G;  // [tap][k][l]
+};
+int build_prefactored(const Problem& P, const RefTensors& T, double dt, Prefactored* out, std::string* msg);
+
+// ---------------------------------------------------------------- device side
+struct DevTensors {  // device copies (FP64), offsets into one buffer
+  const double* Tt;
+  const double* Cc;
+  const double* Bv;
+  const double* Fo;
+  const double* Fn;
+  const double* Cv;
+  const double* CFo;
+  const double* CFn;
+};
+
+struct DevGeom {
+  int d, n0, n1, n2;
+  double h0, h1, h2;
+  double a[3];
+  double g[3][3];
+};
+
+// Launchers (defined in kernels.hip). All return a hipError_t as int.
+int launch_aos_to_soa(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
+int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
+int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, double* W,
+                               const double* G, const int32_t* taps, int ntaps, void* stream);
+int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom& g, double dt,
+                         const double* Q, double* W, const DevTensors& t, const PlanRec* plans,
+                         const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
+int items_per_wave(int d, int M);
+int launch_predict_dense(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
+                         const DevTensors& t, const int32_t* elems, int64_t n_elems, double* scratch,
+                         int64_t scratch_elems, void* stream);
+int launch_correct(int d, int M, int flux, const DevGeom& g, double dt, const double* Q, const double* W,
+                   double* Qout, const DevTensors& t, void* stream);
+int launch_check_finite(const double* x, int64_t n, int32_t* flag, void* stream);
+
+}  // namespace ridg
