@@ -1,0 +1,191 @@
+"""Benchmark of the RIDG hot path on one MI355X.
+
+A step is one full RIDG time step (prediction on every region + correction) of the
+whole mesh. Default workload: 2D solid-body rotation v = (-(y-1/2), x-1/2) on a
+512 x 512 periodic mesh of the unit square, order 4 (10 spatial / 20 space-time
+modes per element, 180-unknown regions), CFL 0.5, seeded compact C-infinity bumps,
+FP64. Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line: space-time DOF-updates/s (elements * theta_T * steps / s),
+per-step p50/p99 latency, the roofline of the dominant kernel (prediction) from
+HIP events recorded by the library on its stream, and the plain CPU oracle timed on
+a bounded sample of the same workload.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+HBM_PEAK_GBS = 8000.0
+METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error; p99 latency"
+
+
+def workload(name):
+    from paper_2101_01231_amd import inputs as I
+    if name == "rotation":
+        return I.rotation_2d()
+    if name == "adv2d":
+        return I.advection_2d()
+    if name == "adv3d":
+        return I.advection_3d()
+    if name == "sine":
+        return I.sine_1d()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def make_problem(wl, precision, solver, refine):
+    from paper_2101_01231_amd import ridg
+    prec = {"fp64": ridg.FP64, "fp32": ridg.FP32_REFINE}[precision]
+    sol = {"auto": ridg.SOLVER_AUTO, "region": ridg.SOLVER_REGION, "prefactored": ridg.SOLVER_PREFACTORED,
+           "dense": ridg.SOLVER_DENSE}[solver]
+    if wl.velocity[0] == "const":
+        return ridg.make_problem(wl.d, wl.n, wl.M, velocity=wl.velocity[1], precision=prec, solver=sol,
+                                 refine_steps=refine)
+    return ridg.make_problem(wl.d, wl.n, wl.M, flux=ridg.FLUX_ROTATION, rot_center=wl.velocity[1],
+                             precision=prec, solver=sol, refine_steps=refine)
+
+
+def cpu_baseline(wl, target_s):
+    """The oracle (plain FP64, quadrature assembly, dense LAPACK region solves) on a square
+    patch of elements of the same workload; rate scaled to ST-DOF-updates/s."""
+    import oracle.scheme as S
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
+    except Exception:
+        threads = 1
+    prob = S.Problem(d=wl.d, n=wl.n, M=wl.M, velocity=wl.velocity)
+    side = 4
+    elapsed = 0.0
+    done = 0
+    while True:
+        els = []
+        c = [k // 2 for k in wl.n]
+        for off in range(side ** wl.d):
+            idx = []
+            r = off
+            for i in range(wl.d):
+                idx.append(c[i] - side // 2 + r % side)
+                r //= side
+            els.append(prob.linear(tuple(idx)))
+        t0 = time.perf_counter()
+        S.step_sampled(prob, wl.q0, wl.dt, els)
+        el = time.perf_counter() - t0
+        elapsed, done = el, len(els)
+        if el * 4 > target_s or side >= min(wl.n):
+            break
+        side *= 2
+    rate = done * prob.theta_t / elapsed
+    return {"value": rate, "unit": "ST-DOF-updates/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"one step (prediction of the sampled elements and their face neighbours + correction) "
+                      f"on a {side}^{wl.d} patch of the {'x'.join(map(str, wl.n))} mesh, {elapsed:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="rotation")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--refine", type=int, default=1)
+    ap.add_argument("--solver", default="auto")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-accuracy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2101_01231_amd import ridg
+
+    wl = workload(args.workload)
+    prob = make_problem(wl, args.precision, args.solver, args.refine)
+    sim = ridg.Simulation(prob, device="cuda:0")
+    info = sim.info
+    sim.set_state(wl.q0)
+    print(f"[bench] {wl.name} n={wl.n} M={wl.M} solver={info.solver} plans={info.n_plans} "
+          f"dense={info.n_dense_elements} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    if args.warmup:
+        sim.step(args.warmup, wl.dt)
+    sim.synchronize()
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    sim.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        starts[s].record(stream)
+        sim.step(1, wl.dt)
+        ends[s].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tim = sim.get_timing()
+    sim.enable_timing(False)
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+
+    st_dof = info.n_elements * info.theta_t * args.steps / wall
+    pred_ms = tim.predict_ms / max(tim.steps, 1)
+    corr_ms = tim.correct_ms / max(tim.steps, 1)
+    achieved = info.flops_predict / (pred_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "prediction (region solves)", "achieved": achieved,
+                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
+                "traffic": None, "flops_per_launch": info.flops_predict, "avg_launch_ms": pred_ms,
+                "correction": {"achieved_tflops": info.flops_correct / (corr_ms * 1e-3) / 1e12,
+                               "achieved_gbs": info.bytes_correct / (corr_ms * 1e-3) / 1e9, "avg_ms": corr_ms}}
+    if info.solver == ridg.SOLVER_PREFACTORED:
+        bw = info.bytes_predict / (pred_ms * 1e-3) / 1e9
+        roofline.update({"bound": "hbm", "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": bw / HBM_PEAK_GBS, "bytes_per_launch": info.bytes_predict})
+
+    out = {
+        "metric": METRIC,
+        "value": st_dof,
+        "unit": "ST-DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64-refine",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": list(wl.n), "order": wl.M, "theta_t": info.theta_t,
+                   "velocity": list(map(str, wl.velocity[1])), "dt": wl.dt, "cfl": 0.5,
+                   "solver": ["auto", "prefactored", "region", "dense"][info.solver], "precision": args.precision},
+        "spatial_dof_updates_per_s": info.n_elements * info.theta * args.steps / wall,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "max": float(lat.max())},
+        "roofline": roofline,
+    }
+    if not args.no_accuracy:
+        q = sim.get_state()
+        T = (args.warmup + args.steps) * wl.dt
+        ex = wl.exact(T)
+        out["rel_l2_vs_exact"] = float(np.linalg.norm(q - ex) / np.linalg.norm(ex))
+        out["final_time"] = T
+    sim.close()
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -101,9 +101,19 @@ typedef struct ridg_info {
   int64_t n_plans;          /* REGION: distinct upwind elimination plans */
   int64_t n_dense_elements; /* REGION: elements solved by the dense path */
   int64_t n_taps;           /* PREFACTORED: non-zero blocks of G (upwind cone) */
-  double flops_per_step;    /* arithmetic of the algorithm actually run (FMA = 2) */
-  double bytes_per_step;    /* algorithmic HBM bytes: state in/out + predictions out/in */
+  double flops_predict;     /* per step, prediction: arithmetic of the algorithm actually run (FMA = 2) */
+  double flops_correct;     /* per step, correction */
+  double bytes_predict;     /* per step, prediction: algorithmic HBM bytes (state in, predictions out) */
+  double bytes_correct;     /* per step, correction: state in/out, predictions in */
 } ridg_info;
+
+/* Accumulated stage times of ridg_step, from HIP events recorded on the handle's stream. */
+typedef struct ridg_timing {
+  int64_t steps;     /* steps timed since the last ridg_get_timing */
+  double predict_ms; /* sum over steps: prediction kernels (rows a1-a5) */
+  double correct_ms; /* sum over steps: correction kernel */
+  double max_step_ms; /* slowest single step (prediction + correction) */
+} ridg_timing;
 
 typedef struct ridg_handle ridg_t;
 
@@ -140,6 +150,13 @@ int ridg_get_prediction(ridg_t* h, double dt, double* w, size_t count, int32_t w
 
 /* Sizes and cost model of the handle. */
 int ridg_get_info(ridg_t* h, ridg_info* info);
+
+/* Switch stage timing on (1) or off (0). When on, ridg_step records a HIP event before the
+ * prediction, between prediction and correction, and after the correction of every step. */
+int ridg_enable_timing(ridg_t* h, int32_t on);
+
+/* Synchronise the stream and return (and reset) the accumulated stage times. */
+int ridg_get_timing(ridg_t* h, ridg_timing* out);
 
 /* Wait for all queued work of the handle. */
 int ridg_synchronize(ridg_t* h);

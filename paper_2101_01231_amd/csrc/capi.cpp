@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 
 #include "ridg_internal.hpp"
 
@@ -134,6 +135,13 @@ struct ridg_handle {
   int32_t* flag = nullptr;
   DevGeom geom{};
   ridg_info info{};
+  // stage timing
+  bool timing = false;
+  std::vector<hipEvent_t> events;  // 3 per timed step
+  size_t ev_used = 0;
+  ~ridg_handle() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -169,8 +177,8 @@ double cfl_number(const Problem& P, double dt) {
   return best;
 }
 
-// flops of the algorithm as run (FMA = 2), per step
-double flops_model(const ridg_handle* h) {
+// flops of the algorithm as run (FMA = 2), per step: {prediction, correction}
+std::pair<double, double> flops_model(const ridg_handle* h, double plan_flops) {
   const Problem& P = h->P;
   const double nel = (double)P.nel, nt = h->T.nt, ns = h->T.ns, d = P.d;
   const double np_active = (P.flux == RIDG_FLUX_CONST) ? 1.0 : (double)P.d;  // p-modes used per direction
@@ -179,24 +187,15 @@ double flops_model(const ridg_handle* h) {
   if (P.solver == RIDG_SOLVER_PREFACTORED) {
     predict = nel * 2.0 * h->ntaps * nt * ns;
   } else {
-    auto per_block = [&](int own_faces, int in_faces) {
-      double assembly = 2.0 * nt * nt * np_active * (d + own_faces);
-      double rhs = 2.0 * nt * ns + in_faces * 2.0 * nt * nt * np_active;
-      double lu = 2.0 / 3.0 * nt * nt * nt + 2.0 * nt * nt;  // elimination of [A|b] + back substitution
-      return assembly + rhs + lu;
-    };
     double nbn = std::pow(3.0, d) * nt;
     double dense_elem = 2.0 / 3.0 * nbn * nbn * nbn + 2.0 * nbn * nbn;
     if (P.solver == RIDG_SOLVER_DENSE) {
       predict = nel * dense_elem;
     } else {
-      // count per plan block from the host plans (items include padding duplicates: use elements)
-      predict = (double)h->info.n_dense_elements * dense_elem;
-      // plan work is tallied in ridg_create (stored in info.flops_per_step beforehand)
-      predict += h->info.flops_per_step;
+      predict = (double)h->info.n_dense_elements * dense_elem + plan_flops;
     }
   }
-  return predict + correct;
+  return {predict, correct};
 }
 
 }  // namespace
@@ -344,15 +343,17 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   I.n_plans = (int64_t)R.plans.size();
   I.n_dense_elements = h->L.n_dense;
   I.n_taps = 0;
-  I.flops_per_step = plan_flops;
   if (P.solver == RIDG_SOLVER_PREFACTORED) {
     PlanRec rec;
     element_plan(P, 0, &rec);
     I.n_taps = rec.nb;
     h->ntaps = rec.nb;
   }
-  I.flops_per_step = flops_model(h);
-  I.bytes_per_step = (double)P.nel * 8.0 * (2.0 * T.ns + 2.0 * T.nt);
+  auto fl = flops_model(h, plan_flops);
+  I.flops_predict = fl.first;
+  I.flops_correct = fl.second;
+  I.bytes_predict = (double)P.nel * 8.0 * (T.ns + T.nt);
+  I.bytes_correct = (double)P.nel * 8.0 * (2.0 * T.ns + T.nt);
   *out = h;
   return RIDG_OK;
 }
@@ -365,6 +366,35 @@ int ridg_destroy(ridg_t* h) {
 int ridg_get_info(ridg_t* h, ridg_info* info) {
   if (!h || !info) return fail(RIDG_E_INVAL, "NULL argument");
   *info = h->info;
+  return RIDG_OK;
+}
+
+int ridg_enable_timing(ridg_t* h, int32_t on) {
+  if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
+  int err = hipStreamSynchronize(h->stream);
+  if (err) return hip_fail(err, "hipStreamSynchronize");
+  h->timing = on != 0;
+  h->ev_used = 0;
+  return RIDG_OK;
+}
+
+int ridg_get_timing(ridg_t* h, ridg_timing* out) {
+  if (!h || !out) return fail(RIDG_E_INVAL, "NULL argument");
+  int err = hipStreamSynchronize(h->stream);
+  if (err) return hip_fail(err, "hipStreamSynchronize");
+  ridg_timing t{};
+  for (size_t s = 0; s + 2 < h->ev_used; s += 3) {
+    float a = 0.f, b = 0.f;
+    err = hipEventElapsedTime(&a, h->events[s], h->events[s + 1]);
+    if (!err) err = hipEventElapsedTime(&b, h->events[s + 1], h->events[s + 2]);
+    if (err) return hip_fail(err, "hipEventElapsedTime");
+    t.steps += 1;
+    t.predict_ms += a;
+    t.correct_ms += b;
+    t.max_step_ms = std::max(t.max_step_ms, (double)a + b);
+  }
+  h->ev_used = 0;
+  *out = t;
   return RIDG_OK;
 }
 
@@ -430,6 +460,16 @@ static int ensure_dt_tables(ridg_t* h, double dt) {
   return RIDG_OK;
 }
 
+static int record_event(ridg_t* h) {
+  if (h->ev_used == h->events.size()) {
+    hipEvent_t e;
+    int err = hipEventCreate(&e);
+    if (err) return err;
+    h->events.push_back(e);
+  }
+  return hipEventRecord(h->events[h->ev_used++], h->stream);
+}
+
 static int run_predict(ridg_t* h, const double* Q, double dt) {
   const Problem& P = h->P;
   int err = 0;
@@ -459,11 +499,23 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
   int rc = ensure_dt_tables(h, dt);
   if (rc) return rc;
   for (int s = 0; s < n_steps; ++s) {
+    if (h->timing) {
+      int err = record_event(h);
+      if (err) return hip_fail(err, "timing event");
+    }
     rc = run_predict(h, h->Q[h->cur], dt);
     if (rc) return rc;
+    if (h->timing) {
+      int err = record_event(h);
+      if (err) return hip_fail(err, "timing event");
+    }
     int err = launch_correct(h->P.d, h->P.M, h->P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt,
                              h->stream);
     if (err) return hip_fail(err, "correction launch");
+    if (h->timing) {
+      err = record_event(h);
+      if (err) return hip_fail(err, "timing event");
+    }
     h->cur ^= 1;
   }
   return cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;

@@ -31,7 +31,8 @@ HOST, DEVICE = 0, 1
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
-    "ridg_get_prediction", "ridg_get_info", "ridg_synchronize", "ridg_destroy",
+    "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_synchronize",
+    "ridg_destroy",
     "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_error_string", "ridg_last_error",
 ]
 
@@ -62,8 +63,19 @@ class RidgInfo(ctypes.Structure):
         ("n_plans", ctypes.c_int64),
         ("n_dense_elements", ctypes.c_int64),
         ("n_taps", ctypes.c_int64),
-        ("flops_per_step", ctypes.c_double),
-        ("bytes_per_step", ctypes.c_double),
+        ("flops_predict", ctypes.c_double),
+        ("flops_correct", ctypes.c_double),
+        ("bytes_predict", ctypes.c_double),
+        ("bytes_correct", ctypes.c_double),
+    ]
+
+
+class RidgTiming(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64),
+        ("predict_ms", ctypes.c_double),
+        ("correct_ms", ctypes.c_double),
+        ("max_step_ms", ctypes.c_double),
     ]
 
 
@@ -92,6 +104,8 @@ def lib():
         L.ridg_get_state.argtypes = [vp, vp, sz, i32]
         L.ridg_get_prediction.argtypes = [vp, dbl, vp, sz, i32]
         L.ridg_get_info.argtypes = [vp, ctypes.POINTER(RidgInfo)]
+        L.ridg_enable_timing.argtypes = [vp, i32]
+        L.ridg_get_timing.argtypes = [vp, ctypes.POINTER(RidgTiming)]
         L.ridg_synchronize.argtypes = [vp]
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
@@ -221,6 +235,14 @@ class Simulation:
         a = np.empty((self.n_el, self.theta_t))
         _check(lib().ridg_get_prediction(self.handle, float(dt), a.ctypes.data, a.size, HOST))
         return a
+
+    def enable_timing(self, on=True):
+        _check(lib().ridg_enable_timing(self.handle, 1 if on else 0))
+
+    def get_timing(self):
+        t = RidgTiming()
+        _check(lib().ridg_get_timing(self.handle, ctypes.byref(t)))
+        return t
 
     def synchronize(self):
         _check(lib().ridg_synchronize(self.handle))
