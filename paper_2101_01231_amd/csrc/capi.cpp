@@ -34,7 +34,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, taps, plans, items, item_plan, dense, scratch, flag, total;
+  size_t q0, q1, w, stage, tens, g, taps, plans, items, item_plan, dense, scratch, flag, ptab, total;
+  size_t ptab_doubles = 0;
   int64_t n_items = 0, n_dense = 0, scratch_elems = 0;
   size_t tens_doubles = 0;
 };
@@ -104,6 +105,11 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
   L.scratch_elems = n_dense > 0 ? std::max<int64_t>(1, std::min<int64_t>(n_dense, kDenseScratchBytes / per)) : 0;
   L.scratch = take(std::max<int64_t>(L.scratch_elems, 1) * per);
   L.flag = take(256);
+  if (P.solver == RIDG_SOLVER_REGION) {
+    const size_t nn = nt * nt;
+    L.ptab_doubles = ((size_t)1 << (2 * P.d)) * nn + (size_t)P.d * 4 * nn + 2 * (size_t)P.d * 2 * nn + 2 * nt;
+  }
+  L.ptab = take(std::max<size_t>(L.ptab_doubles, 1) * 8);
   L.total = off;
   return L;
 }
@@ -135,12 +141,21 @@ struct ridg_handle {
   int32_t* flag = nullptr;
   DevGeom geom{};
   ridg_info info{};
+  PlanTables pt{};
+  double pt_dt = -1.0;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // 3 per timed step
   size_t ev_used = 0;
+  // REGION solver: the dense regions run on a second stream, forked from and joined back to
+  // the caller's stream around the upwind-plan kernel
+  hipStream_t aux = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   ~ridg_handle() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (aux) (void)hipStreamDestroy(aux);
   }
 };
 
@@ -327,6 +342,11 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
     err = hipMemcpyAsync(h->dense, all.data(), all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (!err) err = hipStreamSynchronize(h->stream);
   }
+  if (!err && P.solver == RIDG_SOLVER_REGION && h->L.n_dense && h->L.n_items) {
+    err = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+    if (!err) err = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
+    if (!err) err = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
+  }
   if (!err) err = hipMemsetAsync(h->Q[0], 0, (size_t)P.nel * T.ns * 8, h->stream);
   if (!err) err = hipStreamSynchronize(h->stream);  // host staging vectors go out of scope
   if (err) {
@@ -443,7 +463,35 @@ int ridg_get_state(ridg_t* h, double* q, size_t count, int32_t where) {
   return fail(RIDG_E_INVAL, "where must be RIDG_HOST or RIDG_DEVICE");
 }
 
+static int ensure_plan_tables(ridg_t* h, double dt) {
+  if (h->P.solver != RIDG_SOLVER_REGION || dt == h->pt_dt) return RIDG_OK;
+  HostPlanTables H = build_plan_tables(h->P, h->T, dt);
+  std::vector<double> buf;
+  buf.reserve(h->L.ptab_doubles);
+  double* base = (double*)(h->ws + h->L.ptab);
+  auto push = [&](const std::vector<double>& v) {
+    const double* at = base + buf.size();
+    buf.insert(buf.end(), v.begin(), v.end());
+    return at;
+  };
+  h->pt.A0 = push(H.A0);
+  h->pt.K = push(H.K);
+  h->pt.Fn0 = push(H.Fn0);
+  h->pt.FnC = push(H.FnC);
+  h->pt.cc_val = push(H.cc_val);
+  std::vector<double> idx(H.cc_idx.size(), 0.0);
+  std::memcpy(idx.data(), H.cc_idx.data(), H.cc_idx.size() * 4);  // int32 payload in the last slot
+  h->pt.cc_idx = (const int32_t*)push(idx);
+  if (buf.size() > h->L.ptab_doubles) return fail(RIDG_E_NOMEM, "plan table layout");
+  int err = hipMemcpyAsync(base, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipStreamSynchronize(h->stream);
+  if (err) return hip_fail(err, "upload of plan tables");
+  h->pt_dt = dt;
+  return RIDG_OK;
+}
+
 static int ensure_dt_tables(ridg_t* h, double dt) {
+  if (h->P.solver == RIDG_SOLVER_REGION) return ensure_plan_tables(h, dt);
   if (h->P.solver != RIDG_SOLVER_PREFACTORED || dt == h->g_dt) return RIDG_OK;
   Prefactored pf;
   std::string msg;
@@ -476,12 +524,22 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
   if (P.solver == RIDG_SOLVER_PREFACTORED) {
     err = launch_predict_prefactored(P.d, P.M, h->geom, Q, h->W, h->G, h->host_taps.data(), h->ntaps, h->stream);
   } else if (P.solver == RIDG_SOLVER_REGION) {
-    if (h->L.n_items)
-      err = launch_predict_plans(P.d, P.M, P.precision, P.refine, h->geom, dt, Q, h->W, h->dt, h->plans, h->items,
+    const bool fork = h->L.n_dense && h->L.n_items && h->aux;
+    if (fork) {
+      err = hipEventRecord(h->fork_ev, h->stream);
+      if (!err) err = hipStreamWaitEvent(h->aux, h->fork_ev, 0);
+      if (!err)
+        err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
+                                   h->L.scratch_elems, h->aux);
+      if (!err) err = hipEventRecord(h->join_ev, h->aux);
+    }
+    if (!err && h->L.n_items)
+      err = launch_predict_plans(P.d, P.M, P.precision, P.refine, h->geom, dt, Q, h->W, h->pt, h->plans, h->items,
                                  h->item_plan, h->L.n_items, h->stream);
-    if (!err && h->L.n_dense)
+    if (!err && h->L.n_dense && !fork)
       err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
                                  h->L.scratch_elems, h->stream);
+    if (!err && fork) err = hipStreamWaitEvent(h->stream, h->join_ev, 0);
   } else {
     err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
                                h->L.scratch_elems, h->stream);

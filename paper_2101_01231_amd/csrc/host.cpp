@@ -499,6 +499,80 @@ bool element_plan(const Problem& P, int64_t e, PlanRec* out) {
   return true;
 }
 
+int plan_max_blocks(int d) { return d == 3 ? 8 : (d == 2 ? 9 : 3); }
+
+HostPlanTables build_plan_tables(const Problem& P, const RefTensors& T, double dt) {
+  const int d = P.d, nt = T.nt, ns = T.ns, np = T.np;
+  const size_t nn = (size_t)nt * nt;
+  HostPlanTables H;
+  // transverse slopes of nu_i (identical on every element)
+  double Vs[3][4] = {{0}};
+  {
+    int idx[3] = {0, 0, 0};
+    double c0[3], c[3][3];
+    nu_coeffs(P, idx, dt, c0, c);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Vs[i][1 + j] = c[i][j] / std::sqrt(3.0);
+  }
+  const int nmask = 1 << (2 * d);
+  H.A0.assign((size_t)nmask * nn, 0.0);
+  for (int m = 0; m < nmask; ++m) {
+    double* A = &H.A0[(size_t)m * nn];
+    for (size_t q = 0; q < nn; ++q) A[q] = T.Tt[q];
+    for (int i = 0; i < d; ++i) {
+      const int bits = (m >> (2 * i)) & 3;
+      for (int p = 1; p < np; ++p) {
+        const double v = Vs[i][p];
+        if (v == 0.0 || p == 1 + i) continue;
+        const double* bv = &T.Bv[T.bv(i, p)];
+        for (size_t q = 0; q < nn; ++q) A[q] -= v * bv[q];
+        for (int sd = 0; sd < 2; ++sd) {
+          if (!((bits >> sd) & 1)) continue;
+          const double* fo = &T.Fo[T.f(i, sd ? 1 : -1, p)];
+          for (size_t q = 0; q < nn; ++q) A[q] += v * fo[q];
+        }
+      }
+    }
+  }
+  H.K.assign((size_t)d * 4 * nn, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int bits = 0; bits < 4; ++bits) {
+      double* K = &H.K[((size_t)i * 4 + bits) * nn];
+      const double* bv = &T.Bv[T.bv(i, 0)];
+      for (size_t q = 0; q < nn; ++q) K[q] = -bv[q];
+      for (int sd = 0; sd < 2; ++sd) {
+        if (!((bits >> sd) & 1)) continue;
+        const double* fo = &T.Fo[T.f(i, sd ? 1 : -1, 0)];
+        for (size_t q = 0; q < nn; ++q) K[q] += fo[q];
+      }
+    }
+  H.Fn0.assign((size_t)d * 2 * nn, 0.0);
+  H.FnC.assign((size_t)d * 2 * nn, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s = sd ? 1 : -1;
+      const double* f0 = &T.Fn[T.f(i, s, 0)];
+      double* F0 = &H.Fn0[((size_t)i * 2 + sd) * nn];
+      double* FC = &H.FnC[((size_t)i * 2 + sd) * nn];
+      for (size_t q = 0; q < nn; ++q) F0[q] = f0[q];
+      for (int p = 1; p < np; ++p) {
+        const double v = Vs[i][p];
+        if (v == 0.0 || p == 1 + i) continue;
+        const double* fp = &T.Fn[T.f(i, s, p)];
+        for (size_t q = 0; q < nn; ++q) FC[q] += v * fp[q];
+      }
+    }
+  H.cc_idx.assign(nt, 0);
+  H.cc_val.assign(nt, 0.0);
+  for (int k = 0; k < nt; ++k)
+    for (int l = 0; l < ns; ++l)
+      if (T.Cc[(size_t)k * ns + l] != 0.0) {
+        H.cc_idx[k] = l;
+        H.cc_val[k] = T.Cc[(size_t)k * ns + l];
+      }
+  return H;
+}
+
 RegionPlans build_plans(const Problem& P) {
   RegionPlans R;
   R.elem_plan.assign((size_t)P.nel, -1);
@@ -507,7 +581,7 @@ RegionPlans build_plans(const Problem& P) {
   // For affine fields the plan depends on the element through its axis lines only; a cache
   // keyed by the face-side pattern keeps this linear in the element count.
   for (int64_t e = 0; e < P.nel; ++e) {
-    if (!element_plan(P, e, &rec)) {
+    if (!element_plan(P, e, &rec) || rec.nb > plan_max_blocks(P.d)) {
       R.dense_elems.push_back((int32_t)e);
       continue;
     }

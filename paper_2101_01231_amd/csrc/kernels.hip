@@ -8,6 +8,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "ridg_internal.hpp"
 
@@ -72,6 +73,15 @@ __device__ inline int face_side(const DevGeom& g, const int idx[3], int i, int s
   spread /= hi;
   const double tol = 1e-12 * (fabs(c0) + spread);
   return (s * c0 - spread >= -tol) ? 0 : 1;
+}
+
+// element i of a small register array without dynamic indexing (a select chain)
+template <int D>
+__device__ inline double sel(const double (&v)[D], int i) {
+  double r = v[0];
+#pragma unroll
+  for (int j = 1; j < D; ++j) r = (i == j) ? v[j] : r;
+  return r;
 }
 
 __device__ inline void wave_sync() {
@@ -215,164 +225,223 @@ __global__ __launch_bounds__(256) void correct_kernel(DevGeom g, double dt, cons
 // projected velocity, Sec. 3) is factorised by Gaussian elimination with partial pivoting, the
 // pivot row being found by a segment-wide argmax over lanes; inflow faces inside the region
 // move the upwind neighbour's already-solved W to the right-hand side.
-template <int D, int M>
+template <int D, int M, int E_>
 struct PlanCfg {
   static constexpr int NS = n_space(D, M);
   static constexpr int NT = n_spacetime(D, M);
   static constexpr int NP = D + 1;
   static constexpr int SEG = seg_width(NT);
-  static constexpr int IPW = 64 / SEG;
-  static constexpr int NB = pow3(D);
+  static constexpr int IPW = 64 / SEG;                          // segments per wavefront
+  static constexpr int E = E_;                                  // regions per segment (share tensor loads)
+  static constexpr int NB = D == 3 ? 8 : pow3(D);               // plan blocks (larger plans use the dense path)
   static constexpr int WAVES = 4;
 };
 
-template <int NT, int SEG>
-__device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, double* piv, double* x) {
-  bool used = (k >= NT);
-  int mystep = -1;
+// Segment-wide maximum of a 32-bit key (all lanes of the segment end with the maximum).
+// Within 16 lanes the butterfly uses DPP lane permutations; across 16-lane rows a swizzle
+// (xor 16 inside 32 lanes) and, for a 64-lane segment, the two halves through readlane.
+template <int CTRL>
+__device__ inline unsigned dpp_mov(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int SEG>
+__device__ inline unsigned seg_max(unsigned key) {
+  if (SEG > 1) key = max(key, dpp_mov<0xB1>(key));   // quad_perm [1,0,3,2]
+  if (SEG > 2) key = max(key, dpp_mov<0x4E>(key));   // quad_perm [2,3,0,1]
+  if (SEG > 4) key = max(key, dpp_mov<0x141>(key));  // row_half_mirror
+  if (SEG > 8) key = max(key, dpp_mov<0x140>(key));  // row_mirror
+  if (SEG > 16) key = max(key, (unsigned)__builtin_amdgcn_ds_swizzle((int)key, 0x401F));  // xor 16
+  if (SEG > 32) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)key, 32);
+    key = max(lo, hi);
+  }
+  return key;
+}
+
+// Gaussian elimination with partial pivoting of E systems [A_u | b_u] held row-per-lane in a
+// segment of SEG lanes (rows k < NT). The pivot of column c is the unused row of largest |a_c|,
+// found on a 32-bit key (the FP32 image of |a_c| with the low bits replaced by the lane, so ties
+// go to the lowest row); its row and 1/pivot are published to LDS for the rest of the segment.
+// Solution u is written to x + u * xstride (LDS).
+template <int NT, int SEG, int E>
+__device__ inline void seg_solve(double (&a)[E][NT], double (&rhs)[E], int k, double* piv, double* x, int xstride) {
+  constexpr unsigned LB = SEG <= 1 ? 0 : SEG <= 2 ? 1 : SEG <= 4 ? 2 : SEG <= 8 ? 3 : SEG <= 16 ? 4 : SEG <= 32 ? 5 : 6;
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + 2;  // published row: a[c+1..NT-1], rhs, 1/pivot
+  bool used[E];
+  int mystep[E];
+  double myinv[E];
+#pragma unroll
+  for (int u = 0; u < E; ++u) {
+    used[u] = (k >= NT);
+    mystep[u] = -1;
+    myinv[u] = 0.0;
+  }
 #pragma unroll
   for (int c = 0; c < NT; ++c) {
-    double cand = used ? -1.0 : fabs(a[c]);
-    int idx = k;
 #pragma unroll
-    for (int off = SEG / 2; off > 0; off >>= 1) {
-      const double oc = __shfl_xor(cand, off, SEG);
-      const int oi = __shfl_xor(idx, off, SEG);
-      const bool take = (oc > cand) || (oc == cand && oi < idx);
-      cand = take ? oc : cand;
-      idx = take ? oi : idx;
-    }
-    if (k == idx) {
+    for (int u = 0; u < E; ++u) {
+      unsigned key = 0u;
+      if (!used[u]) key = (__float_as_uint((float)fabs(a[u][c])) & ~LMASK) | (LMASK - (unsigned)k);
+      key = seg_max<SEG>(key);
+      const int p = (int)(LMASK - (key & LMASK));
+      if (k == p) {
+        myinv[u] = 1.0 / a[u][c];
+        double* pv = piv + u * PS;
 #pragma unroll
-      for (int j = c; j < NT; ++j) piv[j] = a[j];
-      piv[NT] = rhs;
-      used = true;
-      mystep = c;
+        for (int j = c + 1; j < NT; ++j) pv[j] = a[u][j];
+        pv[NT] = rhs[u];
+        pv[NT + 1] = myinv[u];
+        used[u] = true;
+        mystep[u] = c;
+      }
     }
     wave_sync();
-    const double inv = 1.0 / piv[c];
-    if (!used) {
-      const double l = a[c] * inv;
 #pragma unroll
-      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, piv[j], a[j]);
-      rhs = fma(-l, piv[NT], rhs);
+    for (int u = 0; u < E; ++u) {
+      if (!used[u]) {
+        const double* pv = piv + u * PS;
+        const double l = a[u][c] * pv[NT + 1];
+#pragma unroll
+        for (int j = c + 1; j < NT; ++j) a[u][j] = fma(-l, pv[j], a[u][j]);
+        rhs[u] = fma(-l, pv[NT], rhs[u]);
+      }
     }
     wave_sync();
   }
 #pragma unroll
   for (int c = NT - 1; c >= 0; --c) {
-    if (mystep == c) x[c] = rhs / a[c];
+#pragma unroll
+    for (int u = 0; u < E; ++u)
+      if (mystep[u] == c) x[u * xstride + c] = rhs[u] * myinv[u];
     wave_sync();
-    const double xc = x[c];
-    if (mystep >= 0 && mystep < c) rhs = fma(-a[c], xc, rhs);
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      const double xc = x[u * xstride + c];
+      if (mystep[u] >= 0 && mystep[u] < c) rhs[u] = fma(-a[u][c], xc, rhs[u]);
+    }
   }
   wave_sync();
 }
 
-template <int D, int M>
+template <int D, int M, int E_>
 __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
-                                                            double* __restrict__ W, DevTensors t,
+                                                            double* __restrict__ W, PlanTables t,
                                                             const PlanRec* __restrict__ plans,
                                                             const int32_t* __restrict__ items,
                                                             const int32_t* __restrict__ item_plan,
                                                             int64_t n_items) {
-  using C = PlanCfg<D, M>;
-  constexpr int NS = C::NS, NT = C::NT, NP = C::NP, SEG = C::SEG, IPW = C::IPW;
-  __shared__ double s_w[C::WAVES][IPW][C::NB][NT];
-  __shared__ double s_piv[C::WAVES][IPW][NT + 1];
+  using C = PlanCfg<D, M, E_>;
+  constexpr int NT = C::NT, SEG = C::SEG, IPW = C::IPW, E = C::E, NB = C::NB;
+  __shared__ double s_w[C::WAVES][IPW][E][NB][NT];
+  __shared__ double s_piv[C::WAVES][IPW][E][NT + 2];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int seg = lane / SEG;
   const int k = lane % SEG;
-  const int64_t item = ((int64_t)blockIdx.x * C::WAVES + wave) * IPW + seg;
-  if (((int64_t)blockIdx.x * C::WAVES + wave) * IPW >= n_items) return;  // whole wave idle
+  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * IPW * E;
+  if (wave_first >= n_items) return;  // whole wavefront idle (the list is padded to IPW * E)
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  int32_t e = items[item];
-  const bool write = e >= 0;
-  if (!write) e = -e - 1;
-  const int pid = __builtin_amdgcn_readfirstlane(item_plan[item]);  // uniform per wave by construction
+  const int64_t item0 = wave_first + (int64_t)seg * E;
+  int32_t e[E];
+  bool wr[E];
+  int base[E][3];
+#pragma unroll
+  for (int u = 0; u < E; ++u) {
+    e[u] = items[item0 + u];
+    wr[u] = e[u] >= 0;
+    if (!wr[u]) e[u] = -e[u] - 1;
+    elem_idx(g, e[u], base[u]);
+  }
+  const int pid = __builtin_amdgcn_readfirstlane(item_plan[wave_first]);  // one plan per wavefront
   const PlanRec* pr = plans + pid;
   const int nb = pr->nb;
-  int base[3];
-  elem_idx(g, e, base);
-  double* sw = &s_w[wave][seg][0][0];
-  double* spiv = &s_piv[wave][seg][0];
+  double* sw = &s_w[wave][seg][0][0][0];
+  double* spiv = &s_piv[wave][seg][0][0];
   const int kr = k < NT ? k : 0;  // padding lanes mirror row 0 (never pivot, never stored)
+  const int ccl = t.cc_idx[kr];
+  const double ccv = t.cc_val[kr];
   for (int b = 0; b < nb; ++b) {
     const PlanBlock blk = pr->blk[b];
-    int gi[3] = {base[0] + blk.off[0], base[1] + blk.off[1], base[2] + blk.off[2]};
-    gi[0] = wrap(gi[0], g.n0);
-    gi[1] = wrap(gi[1], g.n1);
-    gi[2] = wrap(gi[2], g.n2);
-    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
-    double V[D][D + 1];
-    vel_modes<D>(g, gi, dt, V);
-    // row kr of the diagonal block
-    double a[NT];
+    int mask = 0;
 #pragma unroll
-    for (int l = 0; l < NT; ++l) a[l] = t.Tt[kr * NT + l];
+    for (int i = 0; i < D; ++i)
+      mask |= ((blk.src[2 * i] == kOwn ? 1 : 0) | (blk.src[2 * i + 1] == kOwn ? 2 : 0)) << (2 * i);
+    int64_t ge[E];
+    double V0[E][D];
+#pragma unroll
+    for (int u = 0; u < E; ++u) {
+      int gi[3] = {wrap(base[u][0] + blk.off[0], g.n0), wrap(base[u][1] + blk.off[1], g.n1),
+                   wrap(base[u][2] + blk.off[2], g.n2)};
+      ge[u] = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double v = g.a[i];
+#pragma unroll
+        for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
+        V0[u][i] = v * dt / geom_h(g, i);
+      }
+    }
+    // row kr of the diagonal blocks: A0[mask] + sum_i V_i0 K_i[mask_i]
+    double a[E][NT];
+    {
+      const double* a0 = t.A0 + ((size_t)mask * NT + kr) * NT;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        const double v = a0[l];
+#pragma unroll
+        for (int u = 0; u < E; ++u) a[u][l] = v;
+      }
+    }
 #pragma unroll 1
     for (int i = 0; i < D; ++i) {
-#pragma unroll 1
-      for (int p = 0; p < NP; ++p) {
-        if (p == 1 + i) continue;
-        const double vp = V[i][p];
-        if (vp == 0.0) continue;
-        const double* bv = t.Bv + (((size_t)i * NP + p) * NT + kr) * NT;
+      const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT + kr) * NT;
 #pragma unroll
-        for (int l = 0; l < NT; ++l) a[l] = fma(-vp, bv[l], a[l]);
-      }
-#pragma unroll 1
-      for (int sd = 0; sd < 2; ++sd) {
-        if (blk.src[2 * i + sd] != kOwn) continue;
-#pragma unroll 1
-        for (int p = 0; p < NP; ++p) {
-          if (p == 1 + i) continue;
-          const double vp = V[i][p];
-          if (vp == 0.0) continue;
-          const double* fo = t.Fo + ((((size_t)i * 2 + sd) * NP + p) * NT + kr) * NT;
+      for (int l = 0; l < NT; ++l) {
+        const double v = kk[l];
 #pragma unroll
-          for (int l = 0; l < NT; ++l) a[l] = fma(vp, fo[l], a[l]);
-        }
+        for (int u = 0; u < E; ++u) a[u][l] = fma(sel<D>(V0[u], i), v, a[u][l]);
       }
     }
-    // right-hand side: causal source minus the upwind couplings
-    double rhs = 0.0;
+    // right-hand side: causal source minus the upwind couplings to solved blocks
+    double rhs[E];
 #pragma unroll
-    for (int l = 0; l < NS; ++l) {
-      const double c = t.Cc[kr * NS + l];
-      if (c != 0.0) rhs = fma(c, Q[(int64_t)l * nel + ge], rhs);
-    }
+    for (int u = 0; u < E; ++u) rhs[u] = ccv * Q[(int64_t)ccl * nel + ge[u]];
 #pragma unroll 1
     for (int i = 0; i < D; ++i) {
 #pragma unroll 1
       for (int sd = 0; sd < 2; ++sd) {
         const int src = blk.src[2 * i + sd];
         if (src == kOwn) continue;
-        const double* wsrc = sw + src * NT;
-#pragma unroll 1
-        for (int p = 0; p < NP; ++p) {
-          if (p == 1 + i) continue;
-          const double vp = V[i][p];
-          if (vp == 0.0) continue;
-          const double* fn = t.Fn + ((((size_t)i * 2 + sd) * NP + p) * NT + kr) * NT;
-          double s = 0.0;
+        const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + kr) * NT;
+        const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + kr) * NT;
+        double acc[E];
 #pragma unroll
-          for (int l = 0; l < NT; ++l) s = fma(fn[l], wsrc[l], s);
-          rhs = fma(-vp, s, rhs);
+        for (int u = 0; u < E; ++u) acc[u] = 0.0;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          const double v0 = f0[l], vc = fc[l];
+#pragma unroll
+          for (int u = 0; u < E; ++u) acc[u] = fma(fma(sel<D>(V0[u], i), v0, vc), sw[(u * NB + src) * NT + l], acc[u]);
         }
+#pragma unroll
+        for (int u = 0; u < E; ++u) rhs[u] -= acc[u];
       }
     }
-    seg_solve<NT, SEG>(a, rhs, k, spiv, sw + b * NT);
+    seg_solve<NT, SEG, E>(a, rhs, k, spiv, sw + b * NT, NB * NT);
   }
-  if (write && k < NT) W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
+#pragma unroll
+  for (int u = 0; u < E; ++u)
+    if (wr[u] && k < NT) W[(int64_t)k * nel + e[u]] = sw[(u * NB + nb - 1) * NT + k];
 }
 
 // ---------------------------------------------------------------- dense region solve
 // One workgroup per region: the whole 3^d theta_T system (eq. pred_full_system) assembled in a
 // scratch matrix and solved by Gaussian elimination with partial pivoting.
-template <int D, int M>
-__global__ __launch_bounds__(256) void predict_dense_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+template <int D, int M, int THREADS>
+__global__ __launch_bounds__(THREADS) void predict_dense_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                             double* __restrict__ W, DevTensors t,
                                                             const int32_t* __restrict__ elems,
                                                             int64_t first, int64_t count,
@@ -384,9 +453,10 @@ __global__ __launch_bounds__(256) void predict_dense_kernel(DevGeom g, double dt
   const int32_t e = elems[first + slot];
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   double* A = scratch + (size_t)slot * N * LD;  // [N][N+1]: matrix | rhs
-  __shared__ double s_red_v[256];
-  __shared__ int s_red_i[256];
+  __shared__ int s_red_i[THREADS / 64];
   __shared__ double s_x[N];
+  __shared__ double s_l[N];
+  __shared__ double s_piv[LD];
   int base[3];
   elem_idx(g, e, base);
   for (int R = threadIdx.x; R < N; R += blockDim.x) {
@@ -440,46 +510,43 @@ __global__ __launch_bounds__(256) void predict_dense_kernel(DevGeom g, double dt
     row[N] = rhs;
   }
   __syncthreads();
+  // Gaussian elimination with partial pivoting on [A | b]. Pivot: the row of largest |A[r][c]|,
+  // compared on a 32-bit key (FP32 image of |A[r][c]| with the low bits replaced by the row,
+  // ties to the lowest row) reduced within each wavefront by DPP and across wavefronts in LDS.
+  // The pivot row and the column of multipliers are staged in LDS for the rank-1 update.
+  constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : (N <= 1024 ? 10 : 11));
+  constexpr unsigned RMASK = (1u << RB) - 1u;
+  const int nwaves = blockDim.x >> 6;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int c = 0; c < N; ++c) {
-    // pivot search over rows c..N-1 (lowest row on ties)
-    double best = -1.0;
-    int bi = N;
+    unsigned key = 0u;
     for (int R = c + threadIdx.x; R < N; R += blockDim.x) {
-      const double v = fabs(A[(size_t)R * LD + c]);
-      if (v > best) {
-        best = v;
-        bi = R;
-      }
+      const unsigned kk = (__float_as_uint((float)fabs(A[(size_t)R * LD + c])) & ~RMASK) | (RMASK - (unsigned)R);
+      key = max(key, kk);
     }
-    s_red_v[threadIdx.x] = best;
-    s_red_i[threadIdx.x] = bi;
+    key = seg_max<64>(key);
+    if (lane == 0) s_red_i[wid] = (int)key;
     __syncthreads();
-    for (int off = blockDim.x / 2; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) {
-        const double ov = s_red_v[threadIdx.x + off];
-        const int oi = s_red_i[threadIdx.x + off];
-        if (ov > s_red_v[threadIdx.x] || (ov == s_red_v[threadIdx.x] && oi < s_red_i[threadIdx.x])) {
-          s_red_v[threadIdx.x] = ov;
-          s_red_i[threadIdx.x] = oi;
-        }
+    unsigned best = 0u;
+    for (int w = 0; w < nwaves; ++w) best = max(best, (unsigned)s_red_i[w]);
+    const int p = (int)(RMASK - (best & RMASK));
+    // swap rows c and p (columns c..N) and stage the pivot row
+    for (int j = c + threadIdx.x; j < LD; j += blockDim.x) {
+      const double vc = A[(size_t)c * LD + j], vp = A[(size_t)p * LD + j];
+      if (p != c) {
+        A[(size_t)c * LD + j] = vp;
+        A[(size_t)p * LD + j] = vc;
       }
-      __syncthreads();
+      s_piv[j] = vp;
     }
-    const int p = s_red_i[0];
     __syncthreads();
-    if (p != c)
-      for (int j = c + threadIdx.x; j < LD; j += blockDim.x) {
-        const double tmp = A[(size_t)c * LD + j];
-        A[(size_t)c * LD + j] = A[(size_t)p * LD + j];
-        A[(size_t)p * LD + j] = tmp;
-      }
+    const double inv = 1.0 / s_piv[c];
+    for (int R = c + 1 + threadIdx.x; R < N; R += blockDim.x) s_l[R] = A[(size_t)R * LD + c] * inv;
     __syncthreads();
-    const double inv = 1.0 / A[(size_t)c * LD + c];
     const int rows = N - c - 1, cols = LD - c - 1;
-    for (int64_t q = threadIdx.x; q < (int64_t)rows * cols; q += blockDim.x) {
-      const int R = c + 1 + (int)(q / cols), j = c + 1 + (int)(q % cols);
-      const double l = A[(size_t)R * LD + c] * inv;
-      A[(size_t)R * LD + j] = fma(-l, A[(size_t)c * LD + j], A[(size_t)R * LD + j]);
+    for (int q = threadIdx.x; q < rows * cols; q += blockDim.x) {
+      const int R = c + 1 + q / cols, j = c + 1 + q % cols;
+      A[(size_t)R * LD + j] = fma(-s_l[R], s_piv[j], A[(size_t)R * LD + j]);
     }
     __syncthreads();
   }
@@ -568,48 +635,98 @@ int launch_correct(int d, int M, int flux, const DevGeom& g, double dt, const do
   return dispatch_dm<CorrectL>(d, M, flux, g, dt, Q, W, Qout, t, stream);
 }
 
+// Regions per segment: more share each tensor-row load, fewer keep registers and LDS small.
+// Default by size; RIDG_PLAN_E overrides it (1, 2 or 4) for tuning.
+static int plan_e_default(int nt) { return (nt > 4 && nt <= 10) ? 2 : 1; }
+static int plan_e(int nt) {
+  static int env = [] {
+    const char* v = getenv("RIDG_PLAN_E");
+    return v ? atoi(v) : 0;
+  }();
+  int e = (env == 1 || env == 2 || env == 4) ? env : plan_e_default(nt);
+  if (nt > 32 && e > 1) e = 1;
+  return e;
+}
+
 template <int D, int M>
 struct IpwL {
-  static int run() { return PlanCfg<D, M>::IPW; }
+  static int run() {
+    constexpr int NT = n_spacetime(D, M);
+    return (64 / seg_width(NT)) * plan_e(NT);
+  }
 };
 int items_per_wave(int d, int M) { return dispatch_dm<IpwL>(d, M); }
+
+template <int D, int M, int E>
+static int launch_plans_e(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                          const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
+                          void* stream) {
+  using C = PlanCfg<D, M, E>;
+  const int64_t per_block = (int64_t)C::WAVES * C::IPW * C::E;
+  const int64_t blocks = (n_items + per_block - 1) / per_block;
+  if (blocks == 0) return 0;
+  hipLaunchKernelGGL((predict_plans_kernel<D, M, E>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                     (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+  return (int)hipGetLastError();
+}
 
 template <int D, int M>
 struct PlansL {
   static int run(int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
-                 const DevTensors& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
+                 const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
     (void)precision;
     (void)refine;
-    using C = PlanCfg<D, M>;
-    if (C::NT > 64) return (int)hipErrorInvalidValue;
-    const int64_t per_block = (int64_t)C::WAVES * C::IPW;
-    const int64_t blocks = (n_items + per_block - 1) / per_block;
-    if (blocks == 0) return 0;
-    hipLaunchKernelGGL((predict_plans_kernel<D, M>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
-                       (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
-    return (int)hipGetLastError();
+    constexpr int NT = n_spacetime(D, M);
+    if (NT > 64) return (int)hipErrorInvalidValue;
+    const int e = plan_e(NT);
+    if (e == 1) return launch_plans_e<D, M, 1>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+    if constexpr (NT <= 32) {
+      if (e == 2) return launch_plans_e<D, M, 2>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+      if constexpr (NT <= 20)
+        if (e == 4) return launch_plans_e<D, M, 4>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+    }
+    return (int)hipErrorInvalidValue;
   }
 };
 
 int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom& g, double dt, const double* Q,
-                         double* W, const DevTensors& t, const PlanRec* plans, const int32_t* items,
+                         double* W, const PlanTables& t, const PlanRec* plans, const int32_t* items,
                          const int32_t* item_plan, int64_t n_items, void* stream) {
   return dispatch_dm<PlansL>(d, M, precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
 }
 
+// Threads per dense region: RIDG_DENSE_THREADS (256, 512 or 1024) overrides the default 256.
+static int dense_threads() {
+  static int t = [] {
+    const char* v = getenv("RIDG_DENSE_THREADS");
+    int x = v ? atoi(v) : 256;
+    return (x == 512 || x == 1024) ? x : 256;
+  }();
+  return t;
+}
+
 template <int D, int M>
 struct DenseL {
-  static int run(const DevGeom& g, double dt, const double* Q, double* W, const DevTensors& t,
-                 const int32_t* elems, int64_t n_elems, double* scratch, int64_t scratch_elems, void* stream) {
+  template <int T>
+  static int go(const DevGeom& g, double dt, const double* Q, double* W, const DevTensors& t, const int32_t* elems,
+                int64_t n_elems, double* scratch, int64_t scratch_elems, void* stream) {
     for (int64_t first = 0; first < n_elems; first += scratch_elems) {
       const int64_t chunk = (n_elems - first < scratch_elems) ? n_elems - first : scratch_elems;
-      hipLaunchKernelGGL((predict_dense_kernel<D, M>), dim3((unsigned)chunk), dim3(256), 0, (hipStream_t)stream, g,
+      hipLaunchKernelGGL((predict_dense_kernel<D, M, T>), dim3((unsigned)chunk), dim3(T), 0, (hipStream_t)stream, g,
                          dt, Q, W, t, elems, first, n_elems, scratch);
       int err = (int)hipGetLastError();
       if (err) return err;
     }
     return 0;
+  }
+  static int run(const DevGeom& g, double dt, const double* Q, double* W, const DevTensors& t,
+                 const int32_t* elems, int64_t n_elems, double* scratch, int64_t scratch_elems, void* stream) {
+    switch (dense_threads()) {
+      case 1024: return go<1024>(g, dt, Q, W, t, elems, n_elems, scratch, scratch_elems, stream);
+      case 512: return go<512>(g, dt, Q, W, t, elems, n_elems, scratch, scratch_elems, stream);
+      default: return go<256>(g, dt, Q, W, t, elems, n_elems, scratch, scratch_elems, stream);
+    }
   }
 };
 

@@ -141,6 +141,26 @@ struct DevTensors {  // device copies (FP64), offsets into one buffer
   const double* CFn;
 };
 
+// Precombined region-block tensors of the upwind-plan kernel. For an affine velocity the
+// transverse-slope modes V_{i,1+j} are the same on every element, so each diagonal block is
+//   A_rr = A0[mask] + sum_i V_{i,0}(element) K_i[mask_i]
+// with mask = sum_i own_i << 2i, own_i = (own trace on face s=-1) | (own trace on s=+1) << 1.
+struct PlanTables {
+  const double* A0;       // [mask][k][l]  Tt + sum_{i,j} V_{i,1+j} (-Bv[i][1+j] + sum_own Fo[i][s][1+j])   (dt)
+  const double* K;        // [i][mask_i][k][l]  -Bv[i][0] + sum_own Fo[i][s][0]
+  const double* Fn0;      // [i][sd][k][l]  Fn[i][s][0]
+  const double* FnC;      // [i][sd][k][l]  sum_j V_{i,1+j} Fn[i][s][1+j]                                 (dt)
+  const int32_t* cc_idx;  // [k] the spatial mode coupled to Psi_k by the causal source
+  const double* cc_val;   // [k] its coefficient
+};
+
+struct HostPlanTables {
+  std::vector<double> A0, K, Fn0, FnC, cc_val;
+  std::vector<int32_t> cc_idx;
+};
+HostPlanTables build_plan_tables(const Problem& P, const RefTensors& T, double dt);
+int plan_max_blocks(int d);
+
 struct DevGeom {
   int d, n0, n1, n2;
   double h0, h1, h2;
@@ -154,9 +174,9 @@ int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, v
 int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, double* W,
                                const double* G, const int32_t* taps, int ntaps, void* stream);
 int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom& g, double dt,
-                         const double* Q, double* W, const DevTensors& t, const PlanRec* plans,
+                         const double* Q, double* W, const PlanTables& t, const PlanRec* plans,
                          const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
-int items_per_wave(int d, int M);
+int items_per_wave(int d, int M);  // work-list padding multiple (items a wavefront takes at once)
 int launch_predict_dense(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
                          const DevTensors& t, const int32_t* elems, int64_t n_elems, double* scratch,
                          int64_t scratch_elems, void* stream);
