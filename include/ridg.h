@@ -71,7 +71,8 @@ extern "C" {
 #define RIDG_SOLVER_PREFACTORED 1 /* constant v only: W = G Q_region with G = E_c A^-1 C from a host FP64 LU */
 #define RIDG_SOLVER_REGION 2      /* per element: assemble (QQF) and solve the region system by upwind block
                                      elimination with pivoted dense LU per block; regions whose centre lies on
-                                     a dependency cycle use the dense path */
+                                     a dependency cycle tear one block (multi-right-hand-side elimination plus
+                                     one block-sized system), else use the dense path */
 #define RIDG_SOLVER_DENSE 3       /* per element: dense pivoted LU of the whole 3^d theta_T region system */
 
 /* memory kinds for set/get */
@@ -99,7 +100,8 @@ typedef struct ridg_info {
   int32_t solver;     /* resolved RIDG_SOLVER_* */
   int64_t n_elements;
   int64_t n_plans;          /* REGION: distinct upwind elimination plans */
-  int64_t n_dense_elements; /* REGION: elements solved by the dense path */
+  int64_t n_tear_elements;  /* REGION: regions on a dependency cycle solved by tearing one block */
+  int64_t n_dense_elements; /* REGION: regions solved by dense LU of the whole region */
   int64_t n_taps;           /* PREFACTORED: non-zero blocks of G (upwind cone) */
   double flops_predict;     /* per step, prediction: arithmetic of the algorithm actually run (FMA = 2) */
   double flops_correct;     /* per step, correction */

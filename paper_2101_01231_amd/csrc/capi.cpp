@@ -34,7 +34,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, taps, plans, items, item_plan, dense, scratch, flag, ptab, total;
+  size_t q0, q1, w, stage, tens, g, taps, plans, items, item_plan, dense, scratch, flag, ptab, tplans, telems, total;
+  int64_t n_tear = 0;
   size_t ptab_doubles = 0;
   int64_t n_items = 0, n_dense = 0, scratch_elems = 0;
   size_t tens_doubles = 0;
@@ -110,6 +111,9 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
     L.ptab_doubles = ((size_t)1 << (2 * P.d)) * nn + (size_t)P.d * 4 * nn + 2 * (size_t)P.d * 2 * nn + 2 * nt;
   }
   L.ptab = take(std::max<size_t>(L.ptab_doubles, 1) * 8);
+  L.n_tear = (P.solver == RIDG_SOLVER_REGION && R) ? (int64_t)R->tear_elems.size() : 0;
+  L.tplans = take(std::max<int64_t>(L.n_tear, 1) * sizeof(PlanRec));
+  L.telems = take(std::max<int64_t>(L.n_tear, 1) * 4);
   L.total = off;
   return L;
 }
@@ -137,6 +141,8 @@ struct ridg_handle {
   int32_t* items = nullptr;
   int32_t* item_plan = nullptr;
   int32_t* dense = nullptr;
+  PlanRec* tplans = nullptr;
+  int32_t* telems = nullptr;
   double* scratch = nullptr;
   int32_t* flag = nullptr;
   DevGeom geom{};
@@ -287,6 +293,17 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
     }
     for (int32_t pid : R.elem_plan)
       if (pid >= 0) plan_flops += per_plan[pid];
+    // tear regions: eliminated blocks carry 1 + theta_T right-hand sides
+    for (const PlanRec& pr : R.tear_plans) {
+      for (int b = 0; b < pr.nb; ++b) {
+        int own = 0, in = 0;
+        for (int f = 0; f < 2 * P.d; ++f) (pr.blk[b].src[f] == kOwn ? own : in)++;
+        const double rr = (b == 0) ? nt : 1.0 + nt;  // tear equation: coupling products build its matrix
+        plan_flops += 2.0 * nt * nt * np_active * (P.d + own) + 2.0 * nt + in * (2.0 * nt * nt * np_active + 2.0 * nt * rr) +
+                      2.0 / 3.0 * nt * nt * nt + 2.0 * nt * nt * (b == 0 ? 1.0 : 1.0 + nt);
+      }
+      plan_flops += 2.0 * nt * nt;  // W_centre = alpha + B x
+    }
   }
   h->L = make_layout(P, h->T, &R, (int64_t)items.size());
   if (ws_bytes < h->L.total) {
@@ -305,6 +322,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->items = (int32_t*)(h->ws + h->L.items);
   h->item_plan = (int32_t*)(h->ws + h->L.item_plan);
   h->dense = (int32_t*)(h->ws + h->L.dense);
+  h->tplans = (PlanRec*)(h->ws + h->L.tplans);
+  h->telems = (int32_t*)(h->ws + h->L.telems);
   h->scratch = (double*)(h->ws + h->L.scratch);
   h->flag = (int32_t*)(h->ws + h->L.flag);
   // upload tensors
@@ -336,13 +355,18 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
       err = hipMemcpyAsync(h->item_plan, item_plan.data(), item_plan.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (!err && !R.dense_elems.empty())
       err = hipMemcpyAsync(h->dense, R.dense_elems.data(), R.dense_elems.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (!err && !R.tear_elems.empty())
+      err = hipMemcpyAsync(h->tplans, R.tear_plans.data(), R.tear_plans.size() * sizeof(PlanRec), hipMemcpyHostToDevice,
+                           h->stream);
+    if (!err && !R.tear_elems.empty())
+      err = hipMemcpyAsync(h->telems, R.tear_elems.data(), R.tear_elems.size() * 4, hipMemcpyHostToDevice, h->stream);
   } else if (!err && P.solver == RIDG_SOLVER_DENSE) {
     std::vector<int32_t> all((size_t)P.nel);
     for (int64_t e = 0; e < P.nel; ++e) all[(size_t)e] = (int32_t)e;
     err = hipMemcpyAsync(h->dense, all.data(), all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (!err) err = hipStreamSynchronize(h->stream);
   }
-  if (!err && P.solver == RIDG_SOLVER_REGION && h->L.n_dense && h->L.n_items) {
+  if (!err && P.solver == RIDG_SOLVER_REGION && (h->L.n_dense || h->L.n_tear) && h->L.n_items) {
     err = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
     if (!err) err = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
     if (!err) err = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
@@ -362,6 +386,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   I.n_elements = P.nel;
   I.n_plans = (int64_t)R.plans.size();
   I.n_dense_elements = h->L.n_dense;
+  I.n_tear_elements = h->L.n_tear;
   I.n_taps = 0;
   if (P.solver == RIDG_SOLVER_PREFACTORED) {
     PlanRec rec;
@@ -524,21 +549,23 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
   if (P.solver == RIDG_SOLVER_PREFACTORED) {
     err = launch_predict_prefactored(P.d, P.M, h->geom, Q, h->W, h->G, h->host_taps.data(), h->ntaps, h->stream);
   } else if (P.solver == RIDG_SOLVER_REGION) {
-    const bool fork = h->L.n_dense && h->L.n_items && h->aux;
+    // cyclic regions (tear and dense kernels) run beside the plan kernel on a forked stream
+    const bool side = h->L.n_dense || h->L.n_tear;
+    const bool fork = side && h->L.n_items && h->aux;
+    hipStream_t ss = fork ? h->aux : h->stream;
     if (fork) {
       err = hipEventRecord(h->fork_ev, h->stream);
       if (!err) err = hipStreamWaitEvent(h->aux, h->fork_ev, 0);
-      if (!err)
-        err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
-                                   h->L.scratch_elems, h->aux);
-      if (!err) err = hipEventRecord(h->join_ev, h->aux);
     }
     if (!err && h->L.n_items)
       err = launch_predict_plans(P.d, P.M, P.precision, P.refine, h->geom, dt, Q, h->W, h->pt, h->plans, h->items,
                                  h->item_plan, h->L.n_items, h->stream);
-    if (!err && h->L.n_dense && !fork)
+    if (!err && h->L.n_tear)
+      err = launch_predict_tear(P.d, P.M, h->geom, dt, Q, h->W, h->pt, h->tplans, h->telems, h->L.n_tear, ss);
+    if (!err && h->L.n_dense)
       err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
-                                 h->L.scratch_elems, h->stream);
+                                 h->L.scratch_elems, ss);
+    if (!err && fork) err = hipEventRecord(h->join_ev, h->aux);
     if (!err && fork) err = hipStreamWaitEvent(h->stream, h->join_ev, 0);
   } else {
     err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,

@@ -428,37 +428,35 @@ static int offset_code(int d, const int o[3]) {
   return c;
 }
 
-bool element_plan(const Problem& P, int64_t e, PlanRec* out) {
-  const int d = P.d;
-  auto offs = region_offsets(d);
-  const int nb = (int)offs.size();
+// Region dependency graph of element e: pred[r] has bit r' set when block r takes the upwind trace
+// of block r' on some face inside the region (src_of[r][face] = r', -1 for own-trace faces).
+static void region_graph(const Problem& P, int64_t e, const std::vector<std::array<int, 3>>& offs,
+                         uint32_t pred[kMaxBlocks], int src_of[kMaxBlocks][6]) {
+  const int d = P.d, nb = (int)offs.size();
   int base[3];
   element_index(P, e, base);
-  // pred[r] bit r' set: block r takes its upwind trace on some face from block r'
-  uint32_t pred[kMaxBlocks] = {0};
-  int src_of[kMaxBlocks][6];
   for (int r = 0; r < nb; ++r) {
+    pred[r] = 0;
     int g[3];
     wrapped(P, base, offs[r].data(), g);
+    for (int f = 0; f < 6; ++f) src_of[r][f] = -1;
     for (int i = 0; i < d; ++i) {
       for (int s = -1; s <= 1; s += 2) {
-        int f = 2 * i + (s > 0);
-        src_of[r][f] = -1;
         int o2[3] = {offs[r][0], offs[r][1], offs[r][2]};
         o2[i] += s;
         if (o2[i] < -1 || o2[i] > 1) continue;  // region boundary: own trace
-        int side = face_side(P, g, i, s);
-        if (side == 1) {
+        if (face_side(P, g, i, s) == 1) {
           int r2 = offset_code(d, o2);
           pred[r] |= 1u << r2;
-          src_of[r][f] = r2;
+          src_of[r][2 * i + (s > 0)] = r2;
         }
       }
     }
   }
-  int centre = (nb - 1) / 2;
-  // ancestors of the centre
-  uint32_t anc = 1u << centre, frontier = anc;
+}
+
+static uint32_t ancestors(const uint32_t pred[kMaxBlocks], int nb, int root) {
+  uint32_t anc = 1u << root, frontier = anc;
   while (frontier) {
     uint32_t nxt = 0;
     for (int r = 0; r < nb; ++r)
@@ -467,25 +465,37 @@ bool element_plan(const Problem& P, int64_t e, PlanRec* out) {
     anc |= nxt;
     frontier = nxt;
   }
-  // topological order (Kahn, lowest index first)
-  int order[kMaxBlocks], pos[kMaxBlocks];
+  return anc;
+}
+
+// Topological order of the blocks in `set` (Kahn, lowest index first), blocks in `known` being
+// already available; false on a cycle.
+static bool topo_order(const uint32_t pred[kMaxBlocks], int nb, uint32_t set, uint32_t known, int* order,
+                       int* count) {
+  uint32_t done = known;
   int placed = 0;
-  uint32_t done = 0;
-  int count = __builtin_popcount(anc);
-  while (placed < count) {
+  const int want = __builtin_popcount(set);
+  while (placed < want) {
     int pick = -1;
     for (int r = 0; r < nb; ++r) {
-      if (!(anc & (1u << r)) || (done & (1u << r))) continue;
-      if ((pred[r] & anc & ~done) == 0) {
+      if (!(set & (1u << r)) || (done & (1u << r))) continue;
+      if ((pred[r] & (set | known) & ~done) == 0) {
         pick = r;
         break;
       }
     }
-    if (pick < 0) return false;  // dependency cycle among the ancestors
-    pos[pick] = placed;
+    if (pick < 0) return false;
     order[placed++] = pick;
     done |= 1u << pick;
   }
+  *count = placed;
+  return true;
+}
+
+static void fill_plan(const std::vector<std::array<int, 3>>& offs, int d, const int* order, int count,
+                      const int src_of[kMaxBlocks][6], PlanRec* out) {
+  int pos[kMaxBlocks];
+  for (int q = 0; q < count; ++q) pos[order[q]] = q;
   std::memset(out, 0, sizeof(*out));
   out->nb = count;
   for (int q = 0; q < count; ++q) {
@@ -496,7 +506,50 @@ bool element_plan(const Problem& P, int64_t e, PlanRec* out) {
     for (int f = 0; f < 2 * d; ++f)
       if (src_of[r][f] >= 0) b.src[f] = (uint8_t)pos[src_of[r][f]];
   }
+}
+
+bool element_plan(const Problem& P, int64_t e, PlanRec* out) {
+  const int d = P.d;
+  auto offs = region_offsets(d);
+  const int nb = (int)offs.size();
+  uint32_t pred[kMaxBlocks];
+  int src_of[kMaxBlocks][6];
+  region_graph(P, e, offs, pred, src_of);
+  const int centre = (nb - 1) / 2;
+  const uint32_t anc = ancestors(pred, nb, centre);
+  int order[kMaxBlocks], count = 0;
+  if (!topo_order(pred, nb, anc, 0u, order, &count)) return false;  // dependency cycle among the ancestors
+  fill_plan(offs, d, order, count, src_of, out);  // the centre comes last: every other block is its ancestor
   return true;
+}
+
+bool element_tear_plan(const Problem& P, int64_t e, PlanRec* out) {
+  const int d = P.d;
+  auto offs = region_offsets(d);
+  const int nb = (int)offs.size();
+  uint32_t pred[kMaxBlocks];
+  int src_of[kMaxBlocks][6];
+  region_graph(P, e, offs, pred, src_of);
+  const int centre = (nb - 1) / 2;
+  const uint32_t anc = ancestors(pred, nb, centre);
+  for (int t = 0; t < nb; ++t) {
+    if (!(anc & (1u << t))) continue;
+    int order[kMaxBlocks], count = 0;
+    if (!topo_order(pred, nb, anc & ~(1u << t), 1u << t, order + 1, &count)) continue;
+    order[0] = t;  // the tear block is position 0; the others follow in elimination order
+    fill_plan(offs, d, order, count + 1, src_of, out);
+    out->pad[0] = 1;  // one tear block
+    for (int q = 0; q <= count; ++q)
+      if (order[q] == centre) out->pad[1] = q;
+    return true;
+  }
+  return false;
+}
+
+static int n_spacetime_host(int d, int M) {
+  int r = 1;
+  for (int i = 1; i <= d + 1; ++i) r = r * (M + d - (d + 1) + i) / i;
+  return r;
 }
 
 int plan_max_blocks(int d) { return d == 3 ? 8 : (d == 2 ? 9 : 3); }
@@ -582,7 +635,13 @@ RegionPlans build_plans(const Problem& P) {
   // keyed by the face-side pattern keeps this linear in the element count.
   for (int64_t e = 0; e < P.nel; ++e) {
     if (!element_plan(P, e, &rec) || rec.nb > plan_max_blocks(P.d)) {
-      R.dense_elems.push_back((int32_t)e);
+      PlanRec tr;
+      if (n_spacetime_host(P.d, P.M) <= 64 && element_tear_plan(P, e, &tr) && tr.nb <= plan_max_blocks(P.d)) {
+        R.tear_elems.push_back((int32_t)e);
+        R.tear_plans.push_back(tr);
+      } else {
+        R.dense_elems.push_back((int32_t)e);
+      }
       continue;
     }
     std::string key((const char*)&rec, sizeof(rec));

@@ -219,34 +219,33 @@ __global__ __launch_bounds__(256) void correct_kernel(DevGeom g, double dt, cons
 }
 
 // ---------------------------------------------------------------- region solve by upwind plans
-// One segment of SEG lanes (SEG = next power of two >= theta_T) per region; lane k owns row k of
-// each block system. Blocks are solved in the plan's topological order: the diagonal block
-// (time term - internal flux + own-trace faces, assembled from the exact tensors and the
-// projected velocity, Sec. 3) is factorised by Gaussian elimination with partial pivoting, the
-// pivot row being found by a segment-wide argmax over lanes; inflow faces inside the region
-// move the upwind neighbour's already-solved W to the right-hand side.
-template <int D, int M, int E_>
+// A wavefront holds S = floor(64 / theta_T) segments of theta_T consecutive lanes, one region per
+// segment; lane k of a segment owns row k of each block system. Blocks are solved in the plan's
+// topological order: the diagonal block (time term - internal flux + own-trace faces, assembled
+// from precombined exact tensors and the projected velocity, Sec. 3) is eliminated with partial
+// pivoting, the pivot row being found by a segment-wide argmax over lanes; inflow faces inside
+// the region move the upwind neighbour's already-solved W to the right-hand side.
+template <int D, int M>
 struct PlanCfg {
   static constexpr int NS = n_space(D, M);
   static constexpr int NT = n_spacetime(D, M);
-  static constexpr int NP = D + 1;
-  static constexpr int SEG = seg_width(NT);
-  static constexpr int IPW = 64 / SEG;                          // segments per wavefront
-  static constexpr int E = E_;                                  // regions per segment (share tensor loads)
-  static constexpr int NB = D == 3 ? 8 : pow3(D);               // plan blocks (larger plans use the dense path)
+  static constexpr int S = NT <= 64 ? 64 / NT : 1;          // segments (regions) per wavefront
+  static constexpr bool POW2 = (NT & (NT - 1)) == 0;         // segments align with DPP rows
+  static constexpr int LB = NT <= 1 ? 0 : NT <= 2 ? 1 : NT <= 4 ? 2 : NT <= 8 ? 3 : NT <= 16 ? 4 : NT <= 32 ? 5 : 6;
+  static constexpr int NB = D == 3 ? 8 : pow3(D);            // plan blocks (larger plans use the dense path)
   static constexpr int WAVES = 4;
 };
 
-// Segment-wide maximum of a 32-bit key (all lanes of the segment end with the maximum).
-// Within 16 lanes the butterfly uses DPP lane permutations; across 16-lane rows a swizzle
-// (xor 16 inside 32 lanes) and, for a 64-lane segment, the two halves through readlane.
+// Segment-wide maximum of a 32-bit key (every lane of the segment ends with it).
+// Power-of-two segments: butterfly of DPP lane permutations inside 16-lane rows, a swizzle (xor 16)
+// inside 32 lanes and readlane across the two halves of a 64-lane segment.
 template <int CTRL>
 __device__ inline unsigned dpp_mov(unsigned v) {
   return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
 }
 
 template <int SEG>
-__device__ inline unsigned seg_max(unsigned key) {
+__device__ inline unsigned seg_max_pow2(unsigned key) {
   if (SEG > 1) key = max(key, dpp_mov<0xB1>(key));   // quad_perm [1,0,3,2]
   if (SEG > 2) key = max(key, dpp_mov<0x4E>(key));   // quad_perm [2,3,0,1]
   if (SEG > 4) key = max(key, dpp_mov<0x141>(key));  // row_half_mirror
@@ -260,107 +259,106 @@ __device__ inline unsigned seg_max(unsigned key) {
   return key;
 }
 
-// Gaussian elimination with partial pivoting of E systems [A_u | b_u] held row-per-lane in a
-// segment of SEG lanes (rows k < NT). The pivot of column c is the unused row of largest |a_c|,
-// found on a 32-bit key (the FP32 image of |a_c| with the low bits replaced by the lane, so ties
-// go to the lowest row); its row and 1/pivot are published to LDS for the rest of the segment.
-// Solution u is written to x + u * xstride (LDS).
-template <int NT, int SEG, int E>
-__device__ inline void seg_solve(double (&a)[E][NT], double (&rhs)[E], int k, double* piv, double* x, int xstride) {
-  constexpr unsigned LB = SEG <= 1 ? 0 : SEG <= 2 ? 1 : SEG <= 4 ? 2 : SEG <= 8 ? 3 : SEG <= 16 ? 4 : SEG <= 32 ? 5 : 6;
-  constexpr unsigned LMASK = (1u << LB) - 1u;
-  constexpr int PS = NT + 2;  // published row: a[c+1..NT-1], rhs, 1/pivot
-  bool used[E];
-  int mystep[E];
-  double myinv[E];
+// Other segment widths: log2 rounds of a cyclic rotation inside the segment (ds_bpermute); after
+// round r every lane holds the maximum over 2^r consecutive lanes of its segment.
+template <int NT, int LB>
+__device__ inline unsigned seg_max_rot(unsigned key, const int (&addr)[LB > 0 ? LB : 1]) {
 #pragma unroll
-  for (int u = 0; u < E; ++u) {
-    used[u] = (k >= NT);
-    mystep[u] = -1;
-    myinv[u] = 0.0;
-  }
+  for (int r = 0; r < LB; ++r) key = max(key, (unsigned)__builtin_amdgcn_ds_bpermute(addr[r], (int)key));
+  return key;
+}
+
+// 1/x to full FP64 precision: hardware reciprocal estimate and two Newton steps.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Gaussian elimination with partial pivoting of [A | b], row k of A in lane k of the segment.
+// The pivot of column c is the unused row of largest |a_c|, compared on a 32-bit key (the FP32
+// image of |a_c| with its low bits replaced by the row, ties to the lowest row). The pivot row,
+// its right-hand side and 1/pivot are published to LDS for the rest of the segment; the solution
+// is written to x[0..NT-1] (LDS).
+template <int NT, int LB, bool POW2>
+__device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle, const int (&addr)[LB > 0 ? LB : 1],
+                                 double* piv, double* x) {
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  bool used = idle;
+  int mystep = -1;
+  double myinv = 0.0;
 #pragma unroll
   for (int c = 0; c < NT; ++c) {
+    unsigned key = 0u;
+    if (!used) key = (__float_as_uint((float)fabs(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if constexpr (POW2)
+      key = seg_max_pow2<NT>(key);
+    else
+      key = seg_max_rot<NT, LB>(key, addr);
+    const int p = (int)(LMASK - (key & LMASK));
+    if (k == p && !idle) {
+      myinv = recip(a[c]);
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-      unsigned key = 0u;
-      if (!used[u]) key = (__float_as_uint((float)fabs(a[u][c])) & ~LMASK) | (LMASK - (unsigned)k);
-      key = seg_max<SEG>(key);
-      const int p = (int)(LMASK - (key & LMASK));
-      if (k == p) {
-        myinv[u] = 1.0 / a[u][c];
-        double* pv = piv + u * PS;
-#pragma unroll
-        for (int j = c + 1; j < NT; ++j) pv[j] = a[u][j];
-        pv[NT] = rhs[u];
-        pv[NT + 1] = myinv[u];
-        used[u] = true;
-        mystep[u] = c;
-      }
+      for (int j = c + 1; j < NT; ++j) piv[j] = a[j];
+      piv[NT] = rhs;
+      piv[NT + 1] = myinv;
+      used = true;
+      mystep = c;
     }
     wave_sync();
+    if (!used) {
+      const double l = a[c] * piv[NT + 1];
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-      if (!used[u]) {
-        const double* pv = piv + u * PS;
-        const double l = a[u][c] * pv[NT + 1];
-#pragma unroll
-        for (int j = c + 1; j < NT; ++j) a[u][j] = fma(-l, pv[j], a[u][j]);
-        rhs[u] = fma(-l, pv[NT], rhs[u]);
-      }
+      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, piv[j], a[j]);
+      rhs = fma(-l, piv[NT], rhs);
     }
     wave_sync();
   }
 #pragma unroll
   for (int c = NT - 1; c >= 0; --c) {
-#pragma unroll
-    for (int u = 0; u < E; ++u)
-      if (mystep[u] == c) x[u * xstride + c] = rhs[u] * myinv[u];
+    if (mystep == c) x[c] = rhs * myinv;
     wave_sync();
-#pragma unroll
-    for (int u = 0; u < E; ++u) {
-      const double xc = x[u * xstride + c];
-      if (mystep[u] >= 0 && mystep[u] < c) rhs[u] = fma(-a[u][c], xc, rhs[u]);
-    }
+    const double xc = x[c];
+    if (mystep >= 0 && mystep < c) rhs = fma(-a[c], xc, rhs);
   }
   wave_sync();
 }
 
-template <int D, int M, int E_>
+template <int D, int M>
 __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                             double* __restrict__ W, PlanTables t,
                                                             const PlanRec* __restrict__ plans,
                                                             const int32_t* __restrict__ items,
                                                             const int32_t* __restrict__ item_plan,
                                                             int64_t n_items) {
-  using C = PlanCfg<D, M, E_>;
-  constexpr int NT = C::NT, SEG = C::SEG, IPW = C::IPW, E = C::E, NB = C::NB;
-  __shared__ double s_w[C::WAVES][IPW][E][NB][NT];
-  __shared__ double s_piv[C::WAVES][IPW][E][NT + 2];
+  using C = PlanCfg<D, M>;
+  constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB;
+  __shared__ double s_w[C::WAVES][S][NB][NT];
+  __shared__ double s_piv[C::WAVES][S][NT + 2];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int seg = lane / SEG;
-  const int k = lane % SEG;
-  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * IPW * E;
-  if (wave_first >= n_items) return;  // whole wavefront idle (the list is padded to IPW * E)
-  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int64_t item0 = wave_first + (int64_t)seg * E;
-  int32_t e[E];
-  bool wr[E];
-  int base[E][3];
+  const bool idle = lane >= S * NT;  // lanes past the last whole segment
+  const int seg = idle ? 0 : lane / NT;
+  const int k = idle ? lane - S * NT : lane % NT;
+  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S;
+  if (wave_first >= n_items) return;  // whole wavefront idle (the list is padded to S)
+  int addr[LB > 0 ? LB : 1];
 #pragma unroll
-  for (int u = 0; u < E; ++u) {
-    e[u] = items[item0 + u];
-    wr[u] = e[u] >= 0;
-    if (!wr[u]) e[u] = -e[u] - 1;
-    elem_idx(g, e[u], base[u]);
-  }
+  for (int r = 0; r < LB; ++r) addr[r] = 4 * (idle ? lane : seg * NT + (k + (1 << r)) % NT);
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  int32_t e = items[wave_first + seg];
+  const bool write = e >= 0 && !idle;
+  if (e < 0) e = -e - 1;
+  int base[3];
+  elem_idx(g, e, base);
   const int pid = __builtin_amdgcn_readfirstlane(item_plan[wave_first]);  // one plan per wavefront
   const PlanRec* pr = plans + pid;
   const int nb = pr->nb;
-  double* sw = &s_w[wave][seg][0][0][0];
-  double* spiv = &s_piv[wave][seg][0][0];
-  const int kr = k < NT ? k : 0;  // padding lanes mirror row 0 (never pivot, never stored)
+  double* sw = &s_w[wave][seg][0][0];
+  double* spiv = &s_piv[wave][seg][0];
+  const int kr = k < NT ? k : 0;
   const int ccl = t.cc_idx[kr];
   const double ccv = t.cc_val[kr];
   for (int b = 0; b < nb; ++b) {
@@ -369,72 +367,227 @@ __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt
 #pragma unroll
     for (int i = 0; i < D; ++i)
       mask |= ((blk.src[2 * i] == kOwn ? 1 : 0) | (blk.src[2 * i + 1] == kOwn ? 2 : 0)) << (2 * i);
-    int64_t ge[E];
-    double V0[E][D];
+    const int gi[3] = {wrap(base[0] + blk.off[0], g.n0), wrap(base[1] + blk.off[1], g.n1),
+                       wrap(base[2] + blk.off[2], g.n2)};
+    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+    double V0[D];
 #pragma unroll
-    for (int u = 0; u < E; ++u) {
-      int gi[3] = {wrap(base[u][0] + blk.off[0], g.n0), wrap(base[u][1] + blk.off[1], g.n1),
-                   wrap(base[u][2] + blk.off[2], g.n2)};
-      ge[u] = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+    for (int i = 0; i < D; ++i) {
+      double v = g.a[i];
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double v = g.a[i];
-#pragma unroll
-        for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
-        V0[u][i] = v * dt / geom_h(g, i);
-      }
+      for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
+      V0[i] = v * dt / geom_h(g, i);
     }
-    // row kr of the diagonal blocks: A0[mask] + sum_i V_i0 K_i[mask_i]
-    double a[E][NT];
+    // row kr of the diagonal block: A0[mask] + sum_i V_i0 K_i[mask_i]
+    double a[NT];
     {
       const double* a0 = t.A0 + ((size_t)mask * NT + kr) * NT;
 #pragma unroll
-      for (int l = 0; l < NT; ++l) {
-        const double v = a0[l];
-#pragma unroll
-        for (int u = 0; u < E; ++u) a[u][l] = v;
-      }
+      for (int l = 0; l < NT; ++l) a[l] = a0[l];
     }
 #pragma unroll 1
     for (int i = 0; i < D; ++i) {
+      const double vi = sel<D>(V0, i);
       const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT + kr) * NT;
 #pragma unroll
-      for (int l = 0; l < NT; ++l) {
-        const double v = kk[l];
-#pragma unroll
-        for (int u = 0; u < E; ++u) a[u][l] = fma(sel<D>(V0[u], i), v, a[u][l]);
-      }
+      for (int l = 0; l < NT; ++l) a[l] = fma(vi, kk[l], a[l]);
     }
     // right-hand side: causal source minus the upwind couplings to solved blocks
-    double rhs[E];
-#pragma unroll
-    for (int u = 0; u < E; ++u) rhs[u] = ccv * Q[(int64_t)ccl * nel + ge[u]];
+    double rhs = ccv * Q[(int64_t)ccl * nel + ge];
 #pragma unroll 1
     for (int i = 0; i < D; ++i) {
+      const double vi = sel<D>(V0, i);
 #pragma unroll 1
       for (int sd = 0; sd < 2; ++sd) {
         const int src = blk.src[2 * i + sd];
         if (src == kOwn) continue;
         const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + kr) * NT;
         const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + kr) * NT;
-        double acc[E];
+        const double* wsrc = sw + src * NT;
+        double acc = 0.0;
 #pragma unroll
-        for (int u = 0; u < E; ++u) acc[u] = 0.0;
-#pragma unroll
-        for (int l = 0; l < NT; ++l) {
-          const double v0 = f0[l], vc = fc[l];
-#pragma unroll
-          for (int u = 0; u < E; ++u) acc[u] = fma(fma(sel<D>(V0[u], i), v0, vc), sw[(u * NB + src) * NT + l], acc[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < E; ++u) rhs[u] -= acc[u];
+        for (int l = 0; l < NT; ++l) acc = fma(fma(vi, f0[l], fc[l]), wsrc[l], acc);
+        rhs -= acc;
       }
     }
-    seg_solve<NT, SEG, E>(a, rhs, k, spiv, sw + b * NT, NB * NT);
+    seg_solve<NT, LB, C::POW2>(a, rhs, k, idle, addr, spiv, sw + b * NT);
   }
+  if (write) W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
+}
+
+// ---------------------------------------------------------------- cyclic regions by tearing
+// Regions whose centre lies on a dependency cycle (around a point where the flow circulates) are
+// solved on the same block structure: block 0 of the plan is a tear block whose unknowns x break
+// every cycle. The other ancestor blocks are eliminated in upwind order with 1 + theta_T
+// right-hand sides, giving W_r = alpha_r + B_r x; the tear block's own equations then form one
+// theta_T x theta_T system for x, and W_centre = alpha_c + B_c x. This solves exactly the region
+// system of eq. (pred_full_system) restricted to the centre's ancestors.
+template <int NT, int LB, bool POW2, int R>
+__device__ inline void seg_solve_multi(double (&a)[NT], double (&rhs)[R], int k, bool idle,
+                                       const int (&addr)[LB > 0 ? LB : 1], double* piv, double* x) {
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  bool used = idle;
+  int mystep = -1;
+  double myinv = 0.0;
 #pragma unroll
-  for (int u = 0; u < E; ++u)
-    if (wr[u] && k < NT) W[(int64_t)k * nel + e[u]] = sw[(u * NB + nb - 1) * NT + k];
+  for (int c = 0; c < NT; ++c) {
+    unsigned key = 0u;
+    if (!used) key = (__float_as_uint((float)fabs(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if constexpr (POW2)
+      key = seg_max_pow2<(NT > 1 ? NT : 1)>(key);
+    else
+      key = seg_max_rot<NT, LB>(key, addr);
+    const int p = (int)(LMASK - (key & LMASK));
+    if (k == p && !idle) {
+      myinv = recip(a[c]);
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) piv[j] = a[j];
+#pragma unroll
+      for (int j = 0; j < R; ++j) piv[NT + j] = rhs[j];
+      piv[NT + R] = myinv;
+      used = true;
+      mystep = c;
+    }
+    wave_sync();
+    if (!used) {
+      const double l = a[c] * piv[NT + R];
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, piv[j], a[j]);
+#pragma unroll
+      for (int j = 0; j < R; ++j) rhs[j] = fma(-l, piv[NT + j], rhs[j]);
+    }
+    wave_sync();
+  }
+#pragma unroll 1
+  for (int c = NT - 1; c >= 0; --c) {
+    if (mystep == c)
+#pragma unroll
+      for (int j = 0; j < R; ++j) x[c * R + j] = rhs[j] * myinv;
+    wave_sync();
+    if (mystep >= 0 && mystep < c) {
+      double ac = a[0];
+#pragma unroll
+      for (int q = 1; q < NT; ++q) ac = (q == c) ? a[q] : ac;
+#pragma unroll
+      for (int j = 0; j < R; ++j) rhs[j] = fma(-ac, x[c * R + j], rhs[j]);
+    }
+  }
+  wave_sync();
+}
+
+template <int D, int M>
+__global__ __launch_bounds__(64) void predict_tear_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+                                                          double* __restrict__ W, PlanTables t,
+                                                          const PlanRec* __restrict__ plans,
+                                                          const int32_t* __restrict__ elems, int64_t n_elems) {
+  using C = PlanCfg<D, M>;
+  if constexpr (C::NT <= 64) {
+  constexpr int NT = C::NT, NB = C::NB, LB = C::LB, R = 1 + NT;
+  __shared__ double s_w[NB][NT][R];  // [alpha | B] of every eliminated block
+  __shared__ double s_piv[NT + R + 1];
+  __shared__ double s_x[NT];
+  const int64_t item = blockIdx.x;
+  if (item >= n_elems) return;
+  const int lane = threadIdx.x & 63;
+  const bool idle = lane >= NT;
+  const int k = idle ? 0 : lane;
+  int addr[LB > 0 ? LB : 1];
+#pragma unroll
+  for (int r = 0; r < LB; ++r) addr[r] = 4 * (idle ? lane : (k + (1 << r)) % NT);
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int32_t e = elems[item];
+  int base[3];
+  elem_idx(g, e, base);
+  const PlanRec* pr = plans + item;
+  const int nb = pr->nb;
+  const int centre = pr->pad[1];
+  const int ccl = t.cc_idx[k];
+  const double ccv = t.cc_val[k];
+  // blocks in elimination order; block 0 (the tear block) last
+  for (int bb = 1; bb <= nb; ++bb) {
+    const int b = bb < nb ? bb : 0;
+    const PlanBlock blk = pr->blk[b];
+    int mask = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      mask |= ((blk.src[2 * i] == kOwn ? 1 : 0) | (blk.src[2 * i + 1] == kOwn ? 2 : 0)) << (2 * i);
+    const int gi[3] = {wrap(base[0] + blk.off[0], g.n0), wrap(base[1] + blk.off[1], g.n1),
+                       wrap(base[2] + blk.off[2], g.n2)};
+    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+    double V0[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double v = g.a[i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
+      V0[i] = v * dt / geom_h(g, i);
+    }
+    double a[NT];
+    {
+      const double* a0 = t.A0 + ((size_t)mask * NT + k) * NT;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) a[l] = a0[l];
+    }
+#pragma unroll 1
+    for (int i = 0; i < D; ++i) {
+      const double vi = sel<D>(V0, i);
+      const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT + k) * NT;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) a[l] = fma(vi, kk[l], a[l]);
+    }
+    double rhs[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) rhs[j] = 0.0;
+    rhs[0] = ccv * Q[(int64_t)ccl * nel + ge];
+#pragma unroll 1
+    for (int i = 0; i < D; ++i) {
+      const double vi = sel<D>(V0, i);
+#pragma unroll 1
+      for (int sd = 0; sd < 2; ++sd) {
+        const int src = blk.src[2 * i + sd];
+        if (src == kOwn) continue;
+        const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + k) * NT;
+        const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + k) * NT;
+        if (src == 0) {  // coupling to the tear unknowns: -A_{b,0} x
+#pragma unroll
+          for (int l = 0; l < NT; ++l) rhs[1 + l] -= fma(vi, f0[l], fc[l]);
+        } else if (b != 0) {  // -A_{b,s} (alpha_s + B_s x)
+#pragma unroll 1
+          for (int l = 0; l < NT; ++l) {
+            const double cl = fma(vi, f0[l], fc[l]);
+#pragma unroll
+            for (int j = 0; j < R; ++j) rhs[j] = fma(-cl, s_w[src][l][j], rhs[j]);
+          }
+        } else {  // tear equation: A_00 x + A_{0,s} (alpha_s + B_s x) = b_0
+#pragma unroll 1
+          for (int l = 0; l < NT; ++l) {
+            const double cl = fma(vi, f0[l], fc[l]);
+            rhs[0] = fma(-cl, s_w[src][l][0], rhs[0]);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) a[j] = fma(cl, s_w[src][l][1 + j], a[j]);
+          }
+        }
+      }
+    }
+    if (b != 0) {
+      seg_solve_multi<NT, LB, C::POW2, R>(a, rhs, k, idle, addr, s_piv, &s_w[b][0][0]);
+    } else {
+      double r0 = rhs[0];
+      seg_solve<NT, LB, C::POW2>(a, r0, k, idle, addr, s_piv, s_x);
+    }
+  }
+  if (!idle) {
+    double w;
+    if (centre == 0) {
+      w = s_x[k];
+    } else {
+      w = s_w[centre][k][0];
+#pragma unroll
+      for (int j = 0; j < NT; ++j) w = fma(s_w[centre][k][1 + j], s_x[j], w);
+    }
+    W[(int64_t)k * nel + e] = w;
+  }
+  }  // theta_T <= 64
 }
 
 // ---------------------------------------------------------------- dense region solve
@@ -524,7 +677,7 @@ __global__ __launch_bounds__(THREADS) void predict_dense_kernel(DevGeom g, doubl
       const unsigned kk = (__float_as_uint((float)fabs(A[(size_t)R * LD + c])) & ~RMASK) | (RMASK - (unsigned)R);
       key = max(key, kk);
     }
-    key = seg_max<64>(key);
+    key = seg_max_pow2<64>(key);
     if (lane == 0) s_red_i[wid] = (int)key;
     __syncthreads();
     unsigned best = 0u;
@@ -635,40 +788,11 @@ int launch_correct(int d, int M, int flux, const DevGeom& g, double dt, const do
   return dispatch_dm<CorrectL>(d, M, flux, g, dt, Q, W, Qout, t, stream);
 }
 
-// Regions per segment: more share each tensor-row load, fewer keep registers and LDS small.
-// Default by size; RIDG_PLAN_E overrides it (1, 2 or 4) for tuning.
-static int plan_e_default(int nt) { return (nt > 4 && nt <= 10) ? 2 : 1; }
-static int plan_e(int nt) {
-  static int env = [] {
-    const char* v = getenv("RIDG_PLAN_E");
-    return v ? atoi(v) : 0;
-  }();
-  int e = (env == 1 || env == 2 || env == 4) ? env : plan_e_default(nt);
-  if (nt > 32 && e > 1) e = 1;
-  return e;
-}
-
 template <int D, int M>
 struct IpwL {
-  static int run() {
-    constexpr int NT = n_spacetime(D, M);
-    return (64 / seg_width(NT)) * plan_e(NT);
-  }
+  static int run() { return PlanCfg<D, M>::S; }
 };
 int items_per_wave(int d, int M) { return dispatch_dm<IpwL>(d, M); }
-
-template <int D, int M, int E>
-static int launch_plans_e(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
-                          const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
-                          void* stream) {
-  using C = PlanCfg<D, M, E>;
-  const int64_t per_block = (int64_t)C::WAVES * C::IPW * C::E;
-  const int64_t blocks = (n_items + per_block - 1) / per_block;
-  if (blocks == 0) return 0;
-  hipLaunchKernelGGL((predict_plans_kernel<D, M, E>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
-                     (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
-  return (int)hipGetLastError();
-}
 
 template <int D, int M>
 struct PlansL {
@@ -677,16 +801,14 @@ struct PlansL {
                  int64_t n_items, void* stream) {
     (void)precision;
     (void)refine;
-    constexpr int NT = n_spacetime(D, M);
-    if (NT > 64) return (int)hipErrorInvalidValue;
-    const int e = plan_e(NT);
-    if (e == 1) return launch_plans_e<D, M, 1>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
-    if constexpr (NT <= 32) {
-      if (e == 2) return launch_plans_e<D, M, 2>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
-      if constexpr (NT <= 20)
-        if (e == 4) return launch_plans_e<D, M, 4>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
-    }
-    return (int)hipErrorInvalidValue;
+    using C = PlanCfg<D, M>;
+    if (C::NT > 64) return (int)hipErrorInvalidValue;
+    const int64_t per_block = (int64_t)C::WAVES * C::S;
+    const int64_t blocks = (n_items + per_block - 1) / per_block;
+    if (blocks == 0) return 0;
+    hipLaunchKernelGGL((predict_plans_kernel<D, M>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                       (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+    return (int)hipGetLastError();
   }
 };
 
@@ -694,6 +816,23 @@ int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom&
                          double* W, const PlanTables& t, const PlanRec* plans, const int32_t* items,
                          const int32_t* item_plan, int64_t n_items, void* stream) {
   return dispatch_dm<PlansL>(d, M, precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+}
+
+template <int D, int M>
+struct TearL {
+  static int run(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t, const PlanRec* plans,
+                 const int32_t* elems, int64_t n_elems, void* stream) {
+    if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
+    if (n_elems == 0) return 0;
+    hipLaunchKernelGGL((predict_tear_kernel<D, M>), dim3((unsigned)n_elems), dim3(64), 0, (hipStream_t)stream, g, dt,
+                       Q, W, t, plans, elems, n_elems);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_predict_tear(int d, int M, const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                        const PlanRec* plans, const int32_t* elems, int64_t n_elems, void* stream) {
+  return dispatch_dm<TearL>(d, M, g, dt, Q, W, t, plans, elems, n_elems, stream);
 }
 
 // Threads per dense region: RIDG_DENSE_THREADS (256, 512 or 1024) overrides the default 256.

@@ -96,9 +96,11 @@ struct PlanRec {
 };
 
 struct RegionPlans {
-  std::vector<PlanRec> plans;       // distinct plans
-  std::vector<int32_t> elem_plan;   // plan id per element, -1 = centre on a dependency cycle
-  std::vector<int32_t> dense_elems; // elements with elem_plan == -1
+  std::vector<PlanRec> plans;        // distinct acyclic plans
+  std::vector<int32_t> elem_plan;    // plan id per element, -1 = centre on a dependency cycle
+  std::vector<int32_t> tear_elems;   // cyclic regions solved by tearing one block (plan per element)
+  std::vector<PlanRec> tear_plans;   // pad[0] = 1 (tear count), pad[1] = plan position of the centre
+  std::vector<int32_t> dense_elems;  // remaining cyclic regions: dense LU of the whole region
 };
 
 // Offsets of the region blocks, lexicographic with o_1 slowest.
@@ -110,6 +112,9 @@ int64_t element_linear(const Problem& P, const int idx[3]);  // periodic wrap
 RegionPlans build_plans(const Problem& P);
 // Plan of one element (false if its centre lies on a cycle).
 bool element_plan(const Problem& P, int64_t e, PlanRec* out);
+// Cyclic region: a plan whose block 0 is a tear block breaking every cycle among the centre's
+// ancestors, the other ancestors following in elimination order (false if no single block does).
+bool element_tear_plan(const Problem& P, int64_t e, PlanRec* out);
 
 // Host FP64 assembly of the region matrix over the given region blocks (offsets), rows = tests.
 // Interior faces between listed blocks are upwind; faces to unlisted blocks use the own trace
@@ -177,6 +182,9 @@ int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom&
                          const double* Q, double* W, const PlanTables& t, const PlanRec* plans,
                          const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
 int items_per_wave(int d, int M);  // work-list padding multiple (items a wavefront takes at once)
+int launch_predict_tear(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
+                        const PlanTables& t, const PlanRec* plans, const int32_t* elems, int64_t n_elems,
+                        void* stream);
 int launch_predict_dense(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
                          const DevTensors& t, const int32_t* elems, int64_t n_elems, double* scratch,
                          int64_t scratch_elems, void* stream);

@@ -61,6 +61,7 @@ class RidgInfo(ctypes.Structure):
         ("solver", ctypes.c_int32),
         ("n_elements", ctypes.c_int64),
         ("n_plans", ctypes.c_int64),
+        ("n_tear_elements", ctypes.c_int64),
         ("n_dense_elements", ctypes.c_int64),
         ("n_taps", ctypes.c_int64),
         ("flops_predict", ctypes.c_double),
