@@ -225,13 +225,15 @@ __global__ __launch_bounds__(256) void correct_kernel(DevGeom g, double dt, cons
 // from precombined exact tensors and the projected velocity, Sec. 3) is eliminated with partial
 // pivoting, the pivot row being found by a segment-wide argmax over lanes; inflow faces inside
 // the region move the upwind neighbour's already-solved W to the right-hand side.
-template <int D, int M>
+template <int D, int M, bool PADDED = false>
 struct PlanCfg {
   static constexpr int NS = n_space(D, M);
   static constexpr int NT = n_spacetime(D, M);
-  static constexpr int S = NT <= 64 ? 64 / NT : 1;          // segments (regions) per wavefront
-  static constexpr bool POW2 = (NT & (NT - 1)) == 0;         // segments align with DPP rows
-  static constexpr int LB = NT <= 1 ? 0 : NT <= 2 ? 1 : NT <= 4 ? 2 : NT <= 8 ? 3 : NT <= 16 ? 4 : NT <= 32 ? 5 : 6;
+  // segment width: theta_T lanes (packed) or the next power of two (padded, DPP reductions)
+  static constexpr int SEGW = PADDED ? seg_width(NT) : NT;
+  static constexpr int S = SEGW <= 64 ? 64 / SEGW : 1;      // segments (regions) per wavefront
+  static constexpr bool POW2 = (SEGW & (SEGW - 1)) == 0;     // segments align with DPP rows
+  static constexpr int LB = SEGW <= 1 ? 0 : SEGW <= 2 ? 1 : SEGW <= 4 ? 2 : SEGW <= 8 ? 3 : SEGW <= 16 ? 4 : SEGW <= 32 ? 5 : 6;
   static constexpr int NB = D == 3 ? 8 : pow3(D);            // plan blocks (larger plans use the dense path)
   static constexpr int WAVES = 4;
 };
@@ -277,79 +279,79 @@ __device__ inline double recip(double x) {
   return fma(r, e, r);
 }
 
-// Gaussian elimination with partial pivoting of [A | b], row k of A in lane k of the segment.
+// Gauss-Jordan elimination with partial pivoting of [A | b], row k of A in lane k of the segment.
 // The pivot of column c is the unused row of largest |a_c|, compared on a 32-bit key (the FP32
 // image of |a_c| with its low bits replaced by the row, ties to the lowest row). The pivot row,
-// its right-hand side and 1/pivot are published to LDS for the rest of the segment; the solution
-// is written to x[0..NT-1] (LDS).
-template <int NT, int LB, bool POW2>
+// its right-hand side and 1/pivot are published to LDS (two alternating buffers, so one wave-level
+// sync per column suffices) and every other row, earlier pivot rows included, is reduced by it.
+// After the last column, pivot row p_c holds x_c = rhs / a_c, written to x[c] (LDS).
+template <int NT, int LB, bool POW2, int SEGW = NT>
 __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle, const int (&addr)[LB > 0 ? LB : 1],
                                  double* piv, double* x) {
   constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + 2;  // published row: a[c+1..NT-1], rhs, 1/pivot
   bool used = idle;
   int mystep = -1;
   double myinv = 0.0;
 #pragma unroll
   for (int c = 0; c < NT; ++c) {
+    double* pv = piv + (c & 1) * PS;
     unsigned key = 0u;
     if (!used) key = (__float_as_uint((float)fabs(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
     if constexpr (POW2)
-      key = seg_max_pow2<NT>(key);
+      key = seg_max_pow2<SEGW>(key);
     else
-      key = seg_max_rot<NT, LB>(key, addr);
+      key = seg_max_rot<SEGW, LB>(key, addr);
     const int p = (int)(LMASK - (key & LMASK));
-    if (k == p && !idle) {
+    const bool is_piv = (k == p) && !idle;
+    if (is_piv) {
       myinv = recip(a[c]);
+      // one 64-bit store per value: lets the register allocator keep a[] in place
+      volatile __attribute__((address_space(3))) double* vp = (volatile __attribute__((address_space(3))) double*)pv;
 #pragma unroll
-      for (int j = c + 1; j < NT; ++j) piv[j] = a[j];
-      piv[NT] = rhs;
-      piv[NT + 1] = myinv;
+      for (int j = c + 1; j < NT; ++j) vp[j] = a[j];
+      vp[NT] = rhs;
+      vp[NT + 1] = myinv;
       used = true;
       mystep = c;
     }
     wave_sync();
-    if (!used) {
-      const double l = a[c] * piv[NT + 1];
+    if (!is_piv && !idle) {
+      const double l = a[c] * pv[NT + 1];
 #pragma unroll
-      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, piv[j], a[j]);
-      rhs = fma(-l, piv[NT], rhs);
+      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, pv[j], a[j]);
+      rhs = fma(-l, pv[NT], rhs);
     }
-    wave_sync();
   }
-#pragma unroll
-  for (int c = NT - 1; c >= 0; --c) {
-    if (mystep == c) x[c] = rhs * myinv;
-    wave_sync();
-    const double xc = x[c];
-    if (mystep >= 0 && mystep < c) rhs = fma(-a[c], xc, rhs);
-  }
+  if (mystep >= 0) x[mystep] = rhs * myinv;
   wave_sync();
 }
 
-template <int D, int M>
+template <int D, int M, bool PADDED>
 __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                             double* __restrict__ W, PlanTables t,
                                                             const PlanRec* __restrict__ plans,
                                                             const int32_t* __restrict__ items,
                                                             const int32_t* __restrict__ item_plan,
                                                             int64_t n_items) {
-  using C = PlanCfg<D, M>;
-  constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB;
+  using C = PlanCfg<D, M, PADDED>;
+  constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB, SEGW = C::SEGW;
   __shared__ double s_w[C::WAVES][S][NB][NT];
-  __shared__ double s_piv[C::WAVES][S][NT + 2];
+  __shared__ double s_piv[C::WAVES][S][2 * (NT + 2)];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const bool idle = lane >= S * NT;  // lanes past the last whole segment
-  const int seg = idle ? 0 : lane / NT;
-  const int k = idle ? lane - S * NT : lane % NT;
+  const bool tail = lane >= S * SEGW;  // lanes past the last whole segment
+  const int seg = tail ? 0 : lane / SEGW;
+  const int k = tail ? lane - S * SEGW : lane % SEGW;
+  const bool idle = tail || k >= NT;   // no row (tail lanes, padding rows of a padded segment)
   const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S;
   if (wave_first >= n_items) return;  // whole wavefront idle (the list is padded to S)
   int addr[LB > 0 ? LB : 1];
 #pragma unroll
-  for (int r = 0; r < LB; ++r) addr[r] = 4 * (idle ? lane : seg * NT + (k + (1 << r)) % NT);
+  for (int r = 0; r < LB; ++r) addr[r] = 4 * (tail ? lane : seg * SEGW + (k + (1 << r)) % SEGW);
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   int32_t e = items[wave_first + seg];
-  const bool write = e >= 0 && !idle;
+  const bool write = e >= 0 && !idle;  // idle already covers k >= NT
   if (e < 0) e = -e - 1;
   int base[3];
   elem_idx(g, e, base);
@@ -358,7 +360,7 @@ __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt
   const int nb = pr->nb;
   double* sw = &s_w[wave][seg][0][0];
   double* spiv = &s_piv[wave][seg][0];
-  const int kr = k < NT ? k : 0;
+  const int kr = idle ? 0 : k;
   const int ccl = t.cc_idx[kr];
   const double ccv = t.cc_val[kr];
   for (int b = 0; b < nb; ++b) {
@@ -410,7 +412,7 @@ __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt
         rhs -= acc;
       }
     }
-    seg_solve<NT, LB, C::POW2>(a, rhs, k, idle, addr, spiv, sw + b * NT);
+    seg_solve<NT, LB, C::POW2, SEGW>(a, rhs, k, idle, addr, spiv, sw + b * NT);
   }
   if (write) W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
 }
@@ -484,7 +486,7 @@ __global__ __launch_bounds__(64) void predict_tear_kernel(DevGeom g, double dt, 
   if constexpr (C::NT <= 64) {
   constexpr int NT = C::NT, NB = C::NB, LB = C::LB, R = 1 + NT;
   __shared__ double s_w[NB][NT][R];  // [alpha | B] of every eliminated block
-  __shared__ double s_piv[NT + R + 1];
+  __shared__ double s_piv[2 * (NT + R + 1)];
   __shared__ double s_x[NT];
   const int64_t item = blockIdx.x;
   if (item >= n_elems) return;
@@ -788,11 +790,34 @@ int launch_correct(int d, int M, int flux, const DevGeom& g, double dt, const do
   return dispatch_dm<CorrectL>(d, M, flux, g, dt, Q, W, Qout, t, stream);
 }
 
+// Segment layout of the plan kernel: packed theta_T-lane segments (default) or power-of-two
+// segments with DPP reductions (RIDG_PLAN_PADDED=1), chosen once per process.
+static bool plan_padded() {
+  static bool v = [] {
+    const char* e = getenv("RIDG_PLAN_PADDED");
+    return e && atoi(e) == 1;
+  }();
+  return v;
+}
+
 template <int D, int M>
 struct IpwL {
-  static int run() { return PlanCfg<D, M>::S; }
+  static int run() { return plan_padded() ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S; }
 };
 int items_per_wave(int d, int M) { return dispatch_dm<IpwL>(d, M); }
+
+template <int D, int M, bool PADDED>
+static int launch_plans(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                        const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
+                        void* stream) {
+  using C = PlanCfg<D, M, PADDED>;
+  const int64_t per_block = (int64_t)C::WAVES * C::S;
+  const int64_t blocks = (n_items + per_block - 1) / per_block;
+  if (blocks == 0) return 0;
+  hipLaunchKernelGGL((predict_plans_kernel<D, M, PADDED>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                     (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+  return (int)hipGetLastError();
+}
 
 template <int D, int M>
 struct PlansL {
@@ -801,14 +826,9 @@ struct PlansL {
                  int64_t n_items, void* stream) {
     (void)precision;
     (void)refine;
-    using C = PlanCfg<D, M>;
-    if (C::NT > 64) return (int)hipErrorInvalidValue;
-    const int64_t per_block = (int64_t)C::WAVES * C::S;
-    const int64_t blocks = (n_items + per_block - 1) / per_block;
-    if (blocks == 0) return 0;
-    hipLaunchKernelGGL((predict_plans_kernel<D, M>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
-                       (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
-    return (int)hipGetLastError();
+    if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
+    if (plan_padded()) return launch_plans<D, M, true>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+    return launch_plans<D, M, false>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
   }
 };
 
