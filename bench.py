@@ -25,6 +25,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published FP32 vector peak (counts packed FP32, which this build does not use)
 HBM_PEAK_GBS = 8000.0
 METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error; p99 latency"
 
@@ -90,13 +91,52 @@ def cpu_baseline(wl, target_s):
                       f"on a {side}^{wl.d} patch of the {'x'.join(map(str, wl.n))} mesh, {elapsed:.1f} s"}
 
 
+def run_path(wl, precision, solver, refine, steps, warmup, label):
+    """Time one configuration; returns the measurements and the final state."""
+    import torch
+    from paper_2101_01231_amd import ridg
+
+    prob = make_problem(wl, precision, solver, refine)
+    sim = ridg.Simulation(prob, device="cuda:0")
+    info = sim.info
+    sim.set_state(wl.q0)
+    print(f"[bench] {label}: {wl.name} n={wl.n} M={wl.M} solver={info.solver} plans={info.n_plans} "
+          f"tear={info.n_tear_elements} dense={info.n_dense_elements} warmup={warmup} steps={steps}",
+          file=sys.stderr, flush=True)
+    if warmup:
+        sim.step(warmup, wl.dt)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    sim.enable_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        starts[s].record(stream)
+        sim.step(1, wl.dt)
+        ends[s].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tim = sim.get_timing()
+    sim.enable_timing(False)
+    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    q = sim.get_state()
+    sim.close()
+    pred_ms = tim.predict_ms / max(tim.steps, 1)
+    corr_ms = tim.correct_ms / max(tim.steps, 1)
+    return dict(info=info, wall=wall, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q,
+                value=info.n_elements * info.theta_t * steps / wall)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="rotation")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="best", choices=["best", "fp64", "fp32"])
     ap.add_argument("--refine", type=int, default=1)
     ap.add_argument("--solver", default="auto")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -107,80 +147,70 @@ def main():
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
-
-    import torch
     from paper_2101_01231_amd import ridg
 
     wl = workload(args.workload)
-    prob = make_problem(wl, args.precision, args.solver, args.refine)
-    sim = ridg.Simulation(prob, device="cuda:0")
-    info = sim.info
-    sim.set_state(wl.q0)
-    print(f"[bench] {wl.name} n={wl.n} M={wl.M} solver={info.solver} plans={info.n_plans} "
-          f"dense={info.n_dense_elements} warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
-    if args.warmup:
-        sim.step(args.warmup, wl.dt)
-    sim.synchronize()
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    sim.enable_timing(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        starts[s].record(stream)
-        sim.step(1, wl.dt)
-        ends[s].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    tim = sim.get_timing()
-    sim.enable_timing(False)
-    lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-
-    st_dof = info.n_elements * info.theta_t * args.steps / wall
-    pred_ms = tim.predict_ms / max(tim.steps, 1)
-    corr_ms = tim.correct_ms / max(tim.steps, 1)
-    achieved = info.flops_predict / (pred_ms * 1e-3) / 1e12
+    has_fp32 = wl.velocity[0] != "const" or args.solver == "region"
+    want = ["fp64", "fp32"] if (args.precision == "best" and has_fp32) else \
+        (["fp64"] if args.precision == "best" else [args.precision])
+    runs = {p: run_path(wl, p, args.solver, args.refine, args.steps, args.warmup, p) for p in want}
+    T = (args.warmup + args.steps) * wl.dt
+    ex = None
+    if not args.no_accuracy:
+        ex = wl.exact(T)
+        for r in runs.values():
+            r["err"] = float(np.linalg.norm(r["q"] - ex) / np.linalg.norm(ex))
+    # headline: the fastest path whose error vs the exact solution is within 1.05x of FP64's
+    best = "fp64" if "fp64" in runs else want[0]
+    for p, r in runs.items():
+        if r["value"] > runs[best]["value"] and (ex is None or "fp64" not in runs or
+                                                 r["err"] <= 1.05 * runs["fp64"]["err"]):
+            best = p
+    R = runs[best]
+    info = R["info"]
+    achieved = info.flops_predict / (R["pred_ms"] * 1e-3) / 1e12
+    peak = FP64_VECTOR_PEAK_TFLOPS if best == "fp64" else FP32_VECTOR_PEAK_TFLOPS
     roofline = {"bound": "alu", "kernel": "prediction (region solves)", "achieved": achieved,
-                "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_VECTOR_PEAK_TFLOPS,
-                "traffic": None, "flops_per_launch": info.flops_predict, "avg_launch_ms": pred_ms,
-                "correction": {"achieved_tflops": info.flops_correct / (corr_ms * 1e-3) / 1e12,
-                               "achieved_gbs": info.bytes_correct / (corr_ms * 1e-3) / 1e9, "avg_ms": corr_ms}}
+                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "flops_per_launch": info.flops_predict, "avg_launch_ms": R["pred_ms"],
+                "correction": {"achieved_tflops": info.flops_correct / (R["corr_ms"] * 1e-3) / 1e12,
+                               "achieved_gbs": info.bytes_correct / (R["corr_ms"] * 1e-3) / 1e9,
+                               "avg_ms": R["corr_ms"]}}
     if info.solver == ridg.SOLVER_PREFACTORED:
-        bw = info.bytes_predict / (pred_ms * 1e-3) / 1e9
+        bw = info.bytes_predict / (R["pred_ms"] * 1e-3) / 1e9
         roofline.update({"bound": "hbm", "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": bw / HBM_PEAK_GBS, "bytes_per_launch": info.bytes_predict})
-
     out = {
         "metric": METRIC,
-        "value": st_dof,
+        "value": R["value"],
         "unit": "ST-DOF-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall * 1e3 / args.steps,
+        "ms_per_step": R["wall"] * 1e3 / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64-refine",
+        "dtype": "f64" if best == "fp64" else "f32+f64-refine",
         "data": "synthetic",
         "config": {"workload": wl.name, "n": list(wl.n), "order": wl.M, "theta_t": info.theta_t,
                    "velocity": list(map(str, wl.velocity[1])), "dt": wl.dt, "cfl": 0.5,
-                   "solver": ["auto", "prefactored", "region", "dense"][info.solver], "precision": args.precision},
-        "spatial_dof_updates_per_s": info.n_elements * info.theta * args.steps / wall,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "max": float(lat.max())},
+                   "solver": ["auto", "prefactored", "region", "dense"][info.solver], "precision": best,
+                   "refine_steps": args.refine if best == "fp32" else 0},
+        "spatial_dof_updates_per_s": info.n_elements * info.theta * args.steps / R["wall"],
+        "latency_ms": {"p50": float(np.percentile(R["lat"], 50)), "p99": float(np.percentile(R["lat"], 99)),
+                       "max": float(R["lat"].max())},
         "roofline": roofline,
+        "paths": {p: {"value": r["value"], "ms_per_step": r["wall"] * 1e3 / args.steps,
+                      "p99_ms": float(np.percentile(r["lat"], 99)), "prediction_ms": r["pred_ms"],
+                      "rel_l2_vs_exact": r.get("err"),
+                      "rel_l2_vs_fp64": (float(np.linalg.norm(r["q"] - runs["fp64"]["q"]) /
+                                               np.linalg.norm(runs["fp64"]["q"])) if "fp64" in runs else None)}
+                  for p, r in runs.items()},
     }
-    if not args.no_accuracy:
-        q = sim.get_state()
-        T = (args.warmup + args.steps) * wl.dt
-        ex = wl.exact(T)
-        out["rel_l2_vs_exact"] = float(np.linalg.norm(q - ex) / np.linalg.norm(ex))
+    if ex is not None:
+        out["rel_l2_vs_exact"] = R["err"]
         out["final_time"] = T
-    sim.close()
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)

@@ -289,6 +289,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
         for (int f = 0; f < 2 * P.d; ++f) (pr.blk[b].src[f] == kOwn ? own : in)++;
         per_plan[p] += 2.0 * nt * nt * np_active * (P.d + own) + 2.0 * nt * ns + in * 2.0 * nt * nt * np_active +
                        2.0 / 3.0 * nt * nt * nt + 2.0 * nt * nt;
+        if (P.precision == RIDG_FP32_REFINE)  // per sweep: FP64 residual (2 nt^2) + replayed elimination (2 nt^2)
+          per_plan[p] += P.refine * 4.0 * nt * nt;
       }
     }
     for (int32_t pid : R.elem_plan)

@@ -327,13 +327,83 @@ __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle,
   wave_sync();
 }
 
-template <int D, int M, bool PADDED>
+// Reduced-precision variant: Gauss-Jordan with partial pivoting in FP32 on the FP32 image of the
+// FP64-assembled block, then `refine` sweeps of iterative refinement: the residual r = b - A x is
+// formed in FP64 from the FP64 row, and the correction is obtained by replaying the FP32
+// elimination (stored multipliers, same pivot order) on r. x is kept in FP64.
+template <int NT, int LB, bool POW2, int SEGW>
+__device__ inline void seg_solve_f32r(const double (&a64)[NT], double rhs64, int refine, int k, bool idle,
+                                      const int (&addr)[LB > 0 ? LB : 1], double* pivbuf, double* x) {
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + 2;
+  float a[NT], lm[NT];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    a[l] = (float)a64[l];
+    lm[l] = 0.0f;
+  }
+  float r = (float)rhs64;
+  bool used = idle;
+  int mystep = -1;
+  float myinv = 0.0f;
+  float* pbase = (float*)pivbuf;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    float* pv = pbase + (c & 1) * PS;
+    unsigned key = 0u;
+    if (!used) key = (__float_as_uint(fabsf(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if constexpr (POW2)
+      key = seg_max_pow2<SEGW>(key);
+    else
+      key = seg_max_rot<SEGW, LB>(key, addr);
+    const int p = (int)(LMASK - (key & LMASK));
+    const bool is_piv = (k == p) && !idle;
+    if (is_piv) {
+      myinv = 1.0f / a[c];
+      volatile __attribute__((address_space(3))) float* vp = (volatile __attribute__((address_space(3))) float*)pv;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) vp[j] = a[j];
+      vp[NT] = r;
+      vp[NT + 1] = myinv;
+      used = true;
+      mystep = c;
+    }
+    wave_sync();
+    if (!is_piv && !idle) {
+      const float l = a[c] * pv[NT + 1];
+      lm[c] = l;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[j] = fmaf(-l, pv[j], a[j]);
+      r = fmaf(-l, pv[NT], r);
+    }
+  }
+  if (mystep >= 0) x[mystep] = (double)(r * myinv);
+  wave_sync();
+  for (int it = 0; it < refine; ++it) {
+    double res = rhs64;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) res = fma(-a64[l], x[l], res);
+    float rr = idle ? 0.0f : (float)res;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      float* pv = pbase + (c & 1) * PS;
+      if (mystep == c) pv[0] = rr;
+      wave_sync();
+      rr = fmaf(-lm[c], pv[0], rr);  // lm[c] = 0 on the pivot row of column c and on idle lanes
+    }
+    wave_sync();
+    if (mystep >= 0) x[mystep] += (double)(rr * myinv);
+    wave_sync();
+  }
+}
+
+template <int D, int M, bool PADDED, bool F32 = false>
 __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                             double* __restrict__ W, PlanTables t,
                                                             const PlanRec* __restrict__ plans,
                                                             const int32_t* __restrict__ items,
                                                             const int32_t* __restrict__ item_plan,
-                                                            int64_t n_items) {
+                                                            int64_t n_items, int refine) {
   using C = PlanCfg<D, M, PADDED>;
   constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB, SEGW = C::SEGW;
   __shared__ double s_w[C::WAVES][S][NB][NT];
@@ -412,7 +482,10 @@ __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt
         rhs -= acc;
       }
     }
-    seg_solve<NT, LB, C::POW2, SEGW>(a, rhs, k, idle, addr, spiv, sw + b * NT);
+    if constexpr (F32)
+      seg_solve_f32r<NT, LB, C::POW2, SEGW>(a, rhs, refine, k, idle, addr, spiv, sw + b * NT);
+    else
+      seg_solve<NT, LB, C::POW2, SEGW>(a, rhs, k, idle, addr, spiv, sw + b * NT);
   }
   if (write) W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
 }
@@ -807,15 +880,19 @@ struct IpwL {
 int items_per_wave(int d, int M) { return dispatch_dm<IpwL>(d, M); }
 
 template <int D, int M, bool PADDED>
-static int launch_plans(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
-                        const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
-                        void* stream) {
+static int launch_plans(int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
+                        const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
+                        int64_t n_items, void* stream) {
   using C = PlanCfg<D, M, PADDED>;
   const int64_t per_block = (int64_t)C::WAVES * C::S;
   const int64_t blocks = (n_items + per_block - 1) / per_block;
   if (blocks == 0) return 0;
-  hipLaunchKernelGGL((predict_plans_kernel<D, M, PADDED>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
-                     (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+  if (precision == RIDG_FP32_REFINE)
+    hipLaunchKernelGGL((predict_plans_kernel<D, M, PADDED, true>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                       (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items, refine);
+  else
+    hipLaunchKernelGGL((predict_plans_kernel<D, M, PADDED, false>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                       (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items, 0);
   return (int)hipGetLastError();
 }
 
@@ -824,11 +901,10 @@ struct PlansL {
   static int run(int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
                  const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
-    (void)precision;
-    (void)refine;
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
-    if (plan_padded()) return launch_plans<D, M, true>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
-    return launch_plans<D, M, false>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+    if (plan_padded())
+      return launch_plans<D, M, true>(precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+    return launch_plans<D, M, false>(precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
   }
 };
 

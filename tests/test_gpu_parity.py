@@ -204,3 +204,29 @@ def test_error_paths():
         sim.step(-1, 0.01)
     assert sim.step(1, 1.0) == ridg.RIDG_W_UNSTABLE
     sim.close()
+
+
+@pytest.mark.parametrize("refine,tol", [(0, 1e-5), (1, 1e-9), (2, 1e-12)])
+def test_fp32_refine_rotation(refine, tol):
+    """Reduced precision (FP32 block factorisations + FP64-residual refinement) against the FP64
+    oracle: the stated bound per number of refinement sweeps."""
+    n, M = 16, 4
+    vel = ("rotation", (0.5, 0.5))
+    prob = oracle_problem(2, (n, n), M, vel)
+    q0 = I.random_state(2, (n, n), M, seed=21)
+    dt = 1.0 / n
+    ref = S.step(prob, q0, dt, 3)
+    got = run_gpu(2, (n, n), M, vel, q0, dt, 3, ridg.SOLVER_REGION, precision=ridg.FP32_REFINE, refine=refine)
+    err = rel_l2(got, ref)
+    print(f"[fp32] refine={refine} rel-L2 {err:.3e}")
+    assert err <= tol
+
+
+def test_fp32_refine_constant_velocity_region():
+    d, n, M, vel = 2, (12, 10), 3, ("const", (0.7, -0.4))
+    prob = oracle_problem(d, n, M, vel)
+    q0 = I.random_state(d, n, M, seed=22)
+    dt = 0.45 * min(prob.h) / 0.7
+    ref = S.step(prob, q0, dt, 3)
+    got = run_gpu(d, n, M, vel, q0, dt, 3, ridg.SOLVER_REGION, precision=ridg.FP32_REFINE, refine=2)
+    assert rel_l2(got, ref) <= 1e-12
