@@ -1,0 +1,287 @@
+#pragma once
+// Device helpers shared by the HIP kernels of libridg (gfx950 / MI355X): sizes, geometry,
+// velocity projection, segment-wide reductions and the per-lane-row block solvers of the
+// RIDG prediction (Sec. 2.2 of arXiv 2101.01231).
+//
+// State and prediction arrays are coefficient-major in HBM (Q[k * nel + e],
+// W[k * nel + e]) so that neighbouring threads/elements read neighbouring
+// addresses. Element e = i0 + n0 (i1 + n1 i2).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstdlib>
+
+#include "ridg_internal.hpp"
+
+namespace ridg {
+
+// ---------------------------------------------------------------- sizes
+__host__ __device__ constexpr int binom(int n, int k) {
+  int r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+__host__ __device__ constexpr int n_space(int D, int M) { return binom(M - 1 + D, D); }
+__host__ __device__ constexpr int n_spacetime(int D, int M) { return binom(M + D, D + 1); }
+__host__ __device__ constexpr int pow3(int D) { return D == 1 ? 3 : (D == 2 ? 9 : 27); }
+__host__ __device__ constexpr int seg_width(int nt) {
+  return nt <= 1 ? 1 : nt <= 2 ? 2 : nt <= 4 ? 4 : nt <= 8 ? 8 : nt <= 16 ? 16 : nt <= 32 ? 32 : 64;
+}
+
+// ---------------------------------------------------------------- geometry helpers
+__device__ inline void elem_idx(const DevGeom& g, int64_t e, int idx[3]) {
+  idx[0] = (int)(e % g.n0);
+  int64_t r = e / g.n0;
+  idx[1] = (int)(r % g.n1);
+  idx[2] = (int)(r / g.n1);
+}
+
+__device__ inline int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+__device__ inline int64_t elem_lin(const DevGeom& g, int i0, int i1, int i2) {
+  return (int64_t)wrap(i0, g.n0) + (int64_t)g.n0 * ((int64_t)wrap(i1, g.n1) + (int64_t)g.n1 * wrap(i2, g.n2));
+}
+
+__device__ inline double geom_h(const DevGeom& g, int i) { return i == 0 ? g.h0 : (i == 1 ? g.h1 : g.h2); }
+
+// nu_i(xi) = c0[i] + sum_j c[i][j] xi_j; projected on p-modes {1, psi_1(xi_j)}: V[i][0] = c0, V[i][1+j] = c_ij / sqrt3
+template <int D>
+__device__ inline void vel_modes(const DevGeom& g, const int idx[3], double dt, double V[D][D + 1]) {
+  const double inv_sqrt3 = 0.57735026918962576451;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double v = g.a[i];
+#pragma unroll
+    for (int j = 0; j < D; ++j) v += g.g[i][j] * ((idx[j] + 0.5) * geom_h(g, j));
+    const double hi = geom_h(g, i);
+    V[i][0] = v * dt / hi;
+#pragma unroll
+    for (int j = 0; j < D; ++j) V[i][1 + j] = g.g[i][j] * (0.5 * geom_h(g, j)) * dt / hi * inv_sqrt3;
+  }
+}
+
+// upwind side of face (i, s): 0 own trace, 1 neighbour trace (same rule as the host plans)
+template <int D>
+__device__ inline int face_side(const DevGeom& g, const int idx[3], int i, int s) {
+  double v = g.a[i], spread = 0.0;
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    v += g.g[i][j] * ((idx[j] + 0.5) * geom_h(g, j));
+    spread += fabs(g.g[i][j] * (0.5 * geom_h(g, j)));
+  }
+  const double hi = geom_h(g, i);
+  const double c0 = v / hi;
+  spread /= hi;
+  const double tol = 1e-12 * (fabs(c0) + spread);
+  return (s * c0 - spread >= -tol) ? 0 : 1;
+}
+
+// element i of a small register array without dynamic indexing (a select chain)
+template <int D>
+__device__ inline double sel(const double (&v)[D], int i) {
+  double r = v[0];
+#pragma unroll
+  for (int j = 1; j < D; ++j) r = (i == j) ? v[j] : r;
+  return r;
+}
+
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// ---------------------------------------------------------------- region solve by upwind plans
+// A wavefront holds S = floor(64 / theta_T) segments of theta_T consecutive lanes, one region per
+// segment; lane k of a segment owns row k of each block system. Blocks are solved in the plan's
+// topological order: the diagonal block (time term - internal flux + own-trace faces, assembled
+// from precombined exact tensors and the projected velocity, Sec. 3) is eliminated with partial
+// pivoting, the pivot row being found by a segment-wide argmax over lanes; inflow faces inside
+// the region move the upwind neighbour's already-solved W to the right-hand side.
+template <int D, int M, bool PADDED = false>
+struct PlanCfg {
+  static constexpr int NS = n_space(D, M);
+  static constexpr int NT = n_spacetime(D, M);
+  // segment width: theta_T lanes (packed) or the next power of two (padded, DPP reductions)
+  static constexpr int SEGW = PADDED ? seg_width(NT) : NT;
+  static constexpr int S = SEGW <= 64 ? 64 / SEGW : 1;      // segments (regions) per wavefront
+  static constexpr bool POW2 = (SEGW & (SEGW - 1)) == 0;     // segments align with DPP rows
+  static constexpr int LB = SEGW <= 1 ? 0 : SEGW <= 2 ? 1 : SEGW <= 4 ? 2 : SEGW <= 8 ? 3 : SEGW <= 16 ? 4 : SEGW <= 32 ? 5 : 6;
+  static constexpr int NB = D == 3 ? 8 : pow3(D);            // plan blocks (larger plans use the dense path)
+  static constexpr int WAVES = 4;
+};
+
+// Segment-wide maximum of a 32-bit key (every lane of the segment ends with it).
+// Power-of-two segments: butterfly of DPP lane permutations inside 16-lane rows, a swizzle (xor 16)
+// inside 32 lanes and readlane across the two halves of a 64-lane segment.
+template <int CTRL>
+__device__ inline unsigned dpp_mov(unsigned v) {
+  return (unsigned)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+template <int SEG>
+__device__ inline unsigned seg_max_pow2(unsigned key) {
+  if (SEG > 1) key = max(key, dpp_mov<0xB1>(key));   // quad_perm [1,0,3,2]
+  if (SEG > 2) key = max(key, dpp_mov<0x4E>(key));   // quad_perm [2,3,0,1]
+  if (SEG > 4) key = max(key, dpp_mov<0x141>(key));  // row_half_mirror
+  if (SEG > 8) key = max(key, dpp_mov<0x140>(key));  // row_mirror
+  if (SEG > 16) key = max(key, (unsigned)__builtin_amdgcn_ds_swizzle((int)key, 0x401F));  // xor 16
+  if (SEG > 32) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)key, 0);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)key, 32);
+    key = max(lo, hi);
+  }
+  return key;
+}
+
+// Other segment widths: log2 rounds of a cyclic rotation inside the segment (ds_bpermute); after
+// round r every lane holds the maximum over 2^r consecutive lanes of its segment.
+template <int NT, int LB>
+__device__ inline unsigned seg_max_rot(unsigned key, const int (&addr)[LB > 0 ? LB : 1]) {
+#pragma unroll
+  for (int r = 0; r < LB; ++r) key = max(key, (unsigned)__builtin_amdgcn_ds_bpermute(addr[r], (int)key));
+  return key;
+}
+
+// 1/x to full FP64 precision: hardware reciprocal estimate and two Newton steps.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// Gauss-Jordan elimination with partial pivoting of [A | b], row k of A in lane k of the segment.
+// The pivot of column c is the unused row of largest |a_c|, compared on a 32-bit key (the FP32
+// image of |a_c| with its low bits replaced by the row, ties to the lowest row). The pivot row,
+// its right-hand side and 1/pivot are published to LDS (two alternating buffers, so one wave-level
+// sync per column suffices) and every other row, earlier pivot rows included, is reduced by it.
+// After the last column, pivot row p_c holds x_c = rhs / a_c, written to x[c] (LDS).
+template <int NT, int LB, bool POW2, int SEGW = NT>
+__device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle, const int (&addr)[LB > 0 ? LB : 1],
+                                 double* piv, double* x) {
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + 2;  // published row: a[c+1..NT-1], rhs, 1/pivot
+  bool used = idle;
+  int mystep = -1;
+  double myinv = 0.0;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double* pv = piv + (c & 1) * PS;
+    unsigned key = 0u;
+    if (!used) key = (__float_as_uint((float)fabs(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if constexpr (POW2)
+      key = seg_max_pow2<SEGW>(key);
+    else
+      key = seg_max_rot<SEGW, LB>(key, addr);
+    const int p = (int)(LMASK - (key & LMASK));
+    const bool is_piv = (k == p) && !idle;
+    if (is_piv) {
+      myinv = recip(a[c]);
+      // one 64-bit store per value: lets the register allocator keep a[] in place
+      volatile __attribute__((address_space(3))) double* vp = (volatile __attribute__((address_space(3))) double*)pv;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) vp[j] = a[j];
+      vp[NT] = rhs;
+      vp[NT + 1] = myinv;
+      used = true;
+      mystep = c;
+    }
+    wave_sync();
+    if (!is_piv && !idle) {
+      const double l = a[c] * pv[NT + 1];
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, pv[j], a[j]);
+      rhs = fma(-l, pv[NT], rhs);
+    }
+  }
+  if (mystep >= 0) x[mystep] = rhs * myinv;
+  wave_sync();
+}
+
+// Reduced-precision variant: Gauss-Jordan with partial pivoting in FP32 on the FP32 image of the
+// FP64-assembled block, then `refine` sweeps of iterative refinement: the residual r = b - A x is
+// formed in FP64 from the FP64 row, and the correction is obtained by replaying the FP32
+// elimination (stored multipliers, same pivot order) on r. x is kept in FP64.
+template <int NT, int LB, bool POW2, int SEGW>
+__device__ inline void seg_solve_f32r(const double (&a64)[NT], double rhs64, int refine, int k, bool idle,
+                                      const int (&addr)[LB > 0 ? LB : 1], double* pivbuf, double* x) {
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + 2;
+  float a[NT], lm[NT];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    a[l] = (float)a64[l];
+    lm[l] = 0.0f;
+  }
+  float r = (float)rhs64;
+  bool used = idle;
+  int mystep = -1;
+  float myinv = 0.0f;
+  float* pbase = (float*)pivbuf;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    float* pv = pbase + (c & 1) * PS;
+    unsigned key = 0u;
+    if (!used) key = (__float_as_uint(fabsf(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if constexpr (POW2)
+      key = seg_max_pow2<SEGW>(key);
+    else
+      key = seg_max_rot<SEGW, LB>(key, addr);
+    const int p = (int)(LMASK - (key & LMASK));
+    const bool is_piv = (k == p) && !idle;
+    if (is_piv) {
+      myinv = 1.0f / a[c];
+      volatile __attribute__((address_space(3))) float* vp = (volatile __attribute__((address_space(3))) float*)pv;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) vp[j] = a[j];
+      vp[NT] = r;
+      vp[NT + 1] = myinv;
+      used = true;
+      mystep = c;
+    }
+    wave_sync();
+    if (!is_piv && !idle) {
+      const float l = a[c] * pv[NT + 1];
+      lm[c] = l;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[j] = fmaf(-l, pv[j], a[j]);
+      r = fmaf(-l, pv[NT], r);
+    }
+  }
+  if (mystep >= 0) x[mystep] = (double)(r * myinv);
+  wave_sync();
+  for (int it = 0; it < refine; ++it) {
+    double res = rhs64;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) res = fma(-a64[l], x[l], res);
+    float rr = idle ? 0.0f : (float)res;
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+      float* pv = pbase + (c & 1) * PS;
+      if (mystep == c) pv[0] = rr;
+      wave_sync();
+      rr = fmaf(-lm[c], pv[0], rr);  // lm[c] = 0 on the pivot row of column c and on idle lanes
+    }
+    wave_sync();
+    if (mystep >= 0) x[mystep] += (double)(rr * myinv);
+    wave_sync();
+  }
+}
+
+// ---------------------------------------------------------------- dispatch
+template <template <int, int> class F, typename... Args>
+static int dispatch_dm(int d, int M, Args... args) {
+#define RIDG_CASE(DD, MM) \
+  if (d == DD && M == MM) return F<DD, MM>::run(args...);
+  RIDG_CASE(1, 1) RIDG_CASE(1, 2) RIDG_CASE(1, 3) RIDG_CASE(1, 4) RIDG_CASE(1, 5)
+  RIDG_CASE(2, 1) RIDG_CASE(2, 2) RIDG_CASE(2, 3) RIDG_CASE(2, 4) RIDG_CASE(2, 5)
+  RIDG_CASE(3, 1) RIDG_CASE(3, 2) RIDG_CASE(3, 3) RIDG_CASE(3, 4) RIDG_CASE(3, 5)
+#undef RIDG_CASE
+  return (int)hipErrorInvalidValue;
+}
+
+static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace ridg
