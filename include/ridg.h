@@ -160,6 +160,25 @@ int ridg_enable_timing(ridg_t* h, int32_t on);
 /* Synchronise the stream and return (and reset) the accumulated stage times. */
 int ridg_get_timing(ridg_t* h, ridg_timing* out);
 
+/* Execution options (all default 0). Values are 0 or 1.
+ *   RIDG_OPT_GRAPH: replay a captured HIP graph of two steps instead of launching kernels one by
+ *     one (recaptured when dt or an option changes; not used while stage timing is on).
+ *   RIDG_OPT_PLAN_LAYOUT (REGION): 0 = theta_T-lane segments packed in the wavefront, 1 = segments
+ *     padded to a power of two (DPP reductions).
+ *   RIDG_OPT_FUSED (PREFACTORED, meshes whose state and predictions fit in 160 KB of LDS): run all
+ *     n_steps of a ridg_step call in one single-workgroup kernel. */
+#define RIDG_OPT_GRAPH 1
+#define RIDG_OPT_PLAN_LAYOUT 2
+#define RIDG_OPT_FUSED 3
+int ridg_set_option(ridg_t* h, int32_t option, int64_t value);
+int ridg_get_option(ridg_t* h, int32_t option, int64_t* value);
+
+/* Autotuner: time every applicable option set on `steps` steps of size dt (HIP events on the
+ * handle's stream), keep the fastest and restore the state. Results are cached per problem shape
+ * in the process and, when the environment variable RIDG_AUTOTUNE_CACHE names a file, appended to
+ * that file and reused by later processes (*best_ms_per_step is then -1). */
+int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step);
+
 /* Wait for all queued work of the handle. */
 int ridg_synchronize(ridg_t* h);
 

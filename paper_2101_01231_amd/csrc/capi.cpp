@@ -9,6 +9,10 @@
 #include <new>
 #include <string>
 #include <utility>
+#include <array>
+#include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "ridg_internal.hpp"
 
@@ -34,10 +38,11 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, taps, plans, items, item_plan, dense, scratch, flag, ptab, tplans, telems, total;
+  size_t q0, q1, w, stage, tens, g, taps, plans, items[2], item_plan[2], dense, scratch, flag, ptab, tplans, telems,
+      total;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
-  int64_t n_items = 0, n_dense = 0, scratch_elems = 0;
+  int64_t n_items[2] = {0, 0}, n_dense = 0, scratch_elems = 0;
   size_t tens_doubles = 0;
 };
 
@@ -70,7 +75,7 @@ void build_items(const RegionPlans& R, int ipw, std::vector<int32_t>* items, std
   }
 }
 
-Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, int64_t n_items) {
+Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, const int64_t n_items[2]) {
   Layout L;
   const size_t nel = (size_t)P.nel, ns = T.ns, nt = T.nt;
   size_t off = 0;
@@ -96,9 +101,11 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
     n_dense = P.nel;
   }
   L.plans = take(std::max<size_t>(nplans, 1) * sizeof(PlanRec));
-  L.n_items = n_items;
-  L.items = take(std::max<int64_t>(n_items, 1) * 4);
-  L.item_plan = take(std::max<int64_t>(n_items, 1) * 4);
+  for (int l = 0; l < 2; ++l) {
+    L.n_items[l] = n_items[l];
+    L.items[l] = take(std::max<int64_t>(n_items[l], 1) * 4);
+    L.item_plan[l] = take(std::max<int64_t>(n_items[l], 1) * 4);
+  }
   L.n_dense = n_dense;
   L.dense = take(std::max<int64_t>(n_dense, 1) * 4);
   const int64_t N = (int64_t)std::pow(3, P.d) * nt;
@@ -138,8 +145,13 @@ struct ridg_handle {
   double g_dt = -1.0;
   std::vector<int32_t> host_taps;
   PlanRec* plans = nullptr;
-  int32_t* items = nullptr;
-  int32_t* item_plan = nullptr;
+  int32_t* items[2] = {nullptr, nullptr};  // region work lists for the two segment layouts
+  int32_t* item_plan[2] = {nullptr, nullptr};
+  // options (ridg_set_option)
+  int opt_graph = 0, opt_layout = 0, opt_fused = 0;
+  hipGraphExec_t graph[2] = {nullptr, nullptr};  // two captured steps, per state-buffer parity
+  hipStream_t cap = nullptr;                      // internal stream used only for capturing
+  double graph_dt = -1.0;
   int32_t* dense = nullptr;
   PlanRec* tplans = nullptr;
   int32_t* telems = nullptr;
@@ -158,10 +170,13 @@ struct ridg_handle {
   hipStream_t aux = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   ~ridg_handle() {
+    for (int p = 0; p < 2; ++p)
+      if (graph[p]) (void)hipGraphExecDestroy(graph[p]);
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     if (fork_ev) (void)hipEventDestroy(fork_ev);
     if (join_ev) (void)hipEventDestroy(join_ev);
     if (aux) (void)hipStreamDestroy(aux);
+    if (cap) (void)hipStreamDestroy(cap);
   }
 };
 
@@ -221,6 +236,43 @@ std::pair<double, double> flops_model(const ridg_handle* h, double plan_flops) {
 
 }  // namespace
 
+// ---------------------------------------------------------------- autotuner
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, std::array<int, 3>> g_tune_cache;  // problem key -> {graph, layout, fused}
+bool g_tune_file_loaded = false;
+
+std::string tune_key(const ridg_handle* h, int32_t steps) {
+  char buf[256];
+  const Problem& P = h->P;
+  std::snprintf(buf, sizeof(buf), "d%d_n%dx%dx%d_M%d_f%d_s%d_p%d_r%d_k%d", P.d, P.n[0], P.n[1], P.n[2], P.M, P.flux,
+                P.solver, P.precision, P.refine, steps);
+  return buf;
+}
+
+void tune_file_load() {
+  if (g_tune_file_loaded) return;
+  g_tune_file_loaded = true;
+  const char* path = std::getenv("RIDG_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char key[200];
+  int a, b, c;
+  while (std::fscanf(f, "%199s %d %d %d", key, &a, &b, &c) == 4) g_tune_cache[key] = {a, b, c};
+  std::fclose(f);
+}
+
+void tune_file_append(const std::string& key, const std::array<int, 3>& o) {
+  const char* path = std::getenv("RIDG_AUTOTUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s %d %d %d\n", key.c_str(), o[0], o[1], o[2]);
+  std::fclose(f);
+}
+}  // namespace
+
 extern "C" {
 
 const char* ridg_error_string(int code) {
@@ -247,13 +299,15 @@ int ridg_workspace_bytes(const ridg_problem* problem, size_t* bytes) {
   if (rc) return fail(rc, msg);
   Basis B = make_basis(P.d, P.M);
   RefTensors T = make_tensors(B);
-  int64_t n_items = 0;
+  int64_t n_items[2] = {0, 0};
   RegionPlans R;
   if (P.solver == RIDG_SOLVER_REGION) {
     R = build_plans(P);
-    std::vector<int32_t> items, item_plan;
-    build_items(R, items_per_wave(P.d, P.M), &items, &item_plan);
-    n_items = (int64_t)items.size();
+    for (int l = 0; l < 2; ++l) {
+      std::vector<int32_t> it, ip;
+      build_items(R, items_per_wave(P.d, P.M, l), &it, &ip);
+      n_items[l] = (int64_t)it.size();
+    }
   }
   *bytes = make_layout(P, T, &R, n_items).total;
   return RIDG_OK;
@@ -273,11 +327,11 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->B = make_basis(P.d, P.M);
   h->T = make_tensors(h->B);
   RegionPlans R;
-  std::vector<int32_t> items, item_plan;
+  std::vector<int32_t> items[2], item_plan[2];
   double plan_flops = 0.0;
   if (P.solver == RIDG_SOLVER_REGION) {
     R = build_plans(P);
-    build_items(R, items_per_wave(P.d, P.M), &items, &item_plan);
+    for (int l = 0; l < 2; ++l) build_items(R, items_per_wave(P.d, P.M, l), &items[l], &item_plan[l]);
     // flop tally of the plan work actually run (per element, padding excluded)
     const double nt = h->T.nt, ns = h->T.ns;
     const double np_active = (P.flux == RIDG_FLUX_CONST) ? 1.0 : (double)P.d;
@@ -307,7 +361,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
       plan_flops += 2.0 * nt * nt;  // W_centre = alpha + B x
     }
   }
-  h->L = make_layout(P, h->T, &R, (int64_t)items.size());
+  const int64_t n_items[2] = {(int64_t)items[0].size(), (int64_t)items[1].size()};
+  h->L = make_layout(P, h->T, &R, n_items);
   if (ws_bytes < h->L.total) {
     delete h;
     return fail(RIDG_E_NOMEM, "workspace smaller than ridg_workspace_bytes()");
@@ -321,8 +376,10 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->G = (double*)(h->ws + h->L.g);
   h->taps = (int32_t*)(h->ws + h->L.taps);
   h->plans = (PlanRec*)(h->ws + h->L.plans);
-  h->items = (int32_t*)(h->ws + h->L.items);
-  h->item_plan = (int32_t*)(h->ws + h->L.item_plan);
+  for (int l = 0; l < 2; ++l) {
+    h->items[l] = (int32_t*)(h->ws + h->L.items[l]);
+    h->item_plan[l] = (int32_t*)(h->ws + h->L.item_plan[l]);
+  }
   h->dense = (int32_t*)(h->ws + h->L.dense);
   h->tplans = (PlanRec*)(h->ws + h->L.tplans);
   h->telems = (int32_t*)(h->ws + h->L.telems);
@@ -351,10 +408,13 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   if (!err && P.solver == RIDG_SOLVER_REGION) {
     if (!R.plans.empty())
       err = hipMemcpyAsync(h->plans, R.plans.data(), R.plans.size() * sizeof(PlanRec), hipMemcpyHostToDevice, h->stream);
-    if (!err && !items.empty())
-      err = hipMemcpyAsync(h->items, items.data(), items.size() * 4, hipMemcpyHostToDevice, h->stream);
-    if (!err && !item_plan.empty())
-      err = hipMemcpyAsync(h->item_plan, item_plan.data(), item_plan.size() * 4, hipMemcpyHostToDevice, h->stream);
+    for (int l = 0; l < 2 && !err; ++l) {
+      if (!items[l].empty())
+        err = hipMemcpyAsync(h->items[l], items[l].data(), items[l].size() * 4, hipMemcpyHostToDevice, h->stream);
+      if (!err && !item_plan[l].empty())
+        err = hipMemcpyAsync(h->item_plan[l], item_plan[l].data(), item_plan[l].size() * 4, hipMemcpyHostToDevice,
+                             h->stream);
+    }
     if (!err && !R.dense_elems.empty())
       err = hipMemcpyAsync(h->dense, R.dense_elems.data(), R.dense_elems.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (!err && !R.tear_elems.empty())
@@ -368,7 +428,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
     err = hipMemcpyAsync(h->dense, all.data(), all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (!err) err = hipStreamSynchronize(h->stream);
   }
-  if (!err && P.solver == RIDG_SOLVER_REGION && (h->L.n_dense || h->L.n_tear) && h->L.n_items) {
+  if (!err && P.solver == RIDG_SOLVER_REGION && (h->L.n_dense || h->L.n_tear) && h->L.n_items[0]) {
     err = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
     if (!err) err = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
     if (!err) err = hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming);
@@ -553,15 +613,16 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
   } else if (P.solver == RIDG_SOLVER_REGION) {
     // cyclic regions (tear and dense kernels) run beside the plan kernel on a forked stream
     const bool side = h->L.n_dense || h->L.n_tear;
-    const bool fork = side && h->L.n_items && h->aux;
+    const int lay = h->opt_layout;
+    const bool fork = side && h->L.n_items[lay] && h->aux;
     hipStream_t ss = fork ? h->aux : h->stream;
     if (fork) {
       err = hipEventRecord(h->fork_ev, h->stream);
       if (!err) err = hipStreamWaitEvent(h->aux, h->fork_ev, 0);
     }
-    if (!err && h->L.n_items)
-      err = launch_predict_plans(P.d, P.M, P.precision, P.refine, h->geom, dt, Q, h->W, h->pt, h->plans, h->items,
-                                 h->item_plan, h->L.n_items, h->stream);
+    if (!err && h->L.n_items[lay])
+      err = launch_predict_plans(P.d, P.M, lay, P.precision, P.refine, h->geom, dt, Q, h->W, h->pt, h->plans,
+                                 h->items[lay], h->item_plan[lay], h->L.n_items[lay], h->stream);
     if (!err && h->L.n_tear)
       err = launch_predict_tear(P.d, P.M, h->geom, dt, Q, h->W, h->pt, h->tplans, h->telems, h->L.n_tear, ss);
     if (!err && h->L.n_dense)
@@ -576,6 +637,69 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
   return err ? hip_fail(err, "prediction launch") : RIDG_OK;
 }
 
+static int direct_step(ridg_t* h, double dt) {
+  if (h->timing) {
+    int err = record_event(h);
+    if (err) return hip_fail(err, "timing event");
+  }
+  int rc = run_predict(h, h->Q[h->cur], dt);
+  if (rc) return rc;
+  if (h->timing) {
+    int err = record_event(h);
+    if (err) return hip_fail(err, "timing event");
+  }
+  int err = launch_correct(h->P.d, h->P.M, h->P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt,
+                           h->stream);
+  if (err) return hip_fail(err, "correction launch");
+  if (h->timing) {
+    err = record_event(h);
+    if (err) return hip_fail(err, "timing event");
+  }
+  h->cur ^= 1;
+  return RIDG_OK;
+}
+
+static void drop_graphs(ridg_t* h) {
+  for (int p = 0; p < 2; ++p)
+    if (h->graph[p]) {
+      (void)hipGraphExecDestroy(h->graph[p]);
+      h->graph[p] = nullptr;
+    }
+  h->graph_dt = -1.0;
+}
+
+// Capture two consecutive steps starting from state buffer `parity` into an executable graph.
+// The captured work contains kernels and event record/wait nodes only (no memset nodes).
+static int capture_graph(ridg_t* h, double dt, int parity) {
+  // capture on an internal stream (the caller's stream may be the legacy default stream, which
+  // cannot be captured); the graph is then launched on the caller's stream
+  if (!h->cap) {
+    int e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e) return hip_fail(e, "capture stream");
+  }
+  const int saved = h->cur;
+  const bool saved_timing = h->timing;
+  hipStream_t user = h->stream;
+  h->timing = false;
+  h->cur = parity;
+  h->stream = h->cap;
+  int err = hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal);
+  int rc = RIDG_OK;
+  if (!err) {
+    rc = direct_step(h, dt);
+    if (!rc) rc = direct_step(h, dt);
+    hipGraph_t g = nullptr;
+    err = hipStreamEndCapture(h->cap, &g);
+    if (!err && !rc) err = hipGraphInstantiate(&h->graph[parity], g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+  }
+  h->stream = user;
+  h->cur = saved;
+  h->timing = saved_timing;
+  if (rc) return rc;
+  return err ? hip_fail(err, "graph capture") : RIDG_OK;
+}
+
 int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
   if (n_steps < 0) return fail(RIDG_E_INVAL, "n_steps must be >= 0");
@@ -585,27 +709,145 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
     return fail(RIDG_E_UNSUPPORTED, "REGION solver supports theta_T <= 64");
   int rc = ensure_dt_tables(h, dt);
   if (rc) return rc;
-  for (int s = 0; s < n_steps; ++s) {
-    if (h->timing) {
-      int err = record_event(h);
-      if (err) return hip_fail(err, "timing event");
-    }
-    rc = run_predict(h, h->Q[h->cur], dt);
-    if (rc) return rc;
-    if (h->timing) {
-      int err = record_event(h);
-      if (err) return hip_fail(err, "timing event");
-    }
-    int err = launch_correct(h->P.d, h->P.M, h->P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt,
-                             h->stream);
-    if (err) return hip_fail(err, "correction launch");
-    if (h->timing) {
-      err = record_event(h);
-      if (err) return hip_fail(err, "timing event");
-    }
+  const int warn = cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;
+  if (h->opt_fused && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && fused_fits(h->P.d, h->P.M, h->P.nel)) {
+    int err = launch_fused_prefactored(h->P.d, h->P.M, h->geom, dt, h->Q[h->cur], h->Q[1 - h->cur], h->G,
+                                       h->host_taps.data(), h->ntaps, h->dt, n_steps, h->stream);
+    if (err) return hip_fail(err, "fused launch");
     h->cur ^= 1;
+    return warn;
   }
-  return cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;
+  if (h->opt_graph && !h->timing && n_steps >= 2) {
+    if (h->graph_dt != dt) drop_graphs(h);
+    h->graph_dt = dt;
+    while (n_steps >= 2) {
+      if (!h->graph[h->cur]) {
+        rc = capture_graph(h, dt, h->cur);
+        if (rc) return rc;
+      }
+      int err = hipGraphLaunch(h->graph[h->cur], h->stream);
+      if (err) return hip_fail(err, "graph launch");
+      n_steps -= 2;  // two steps: the state returns to the same buffer
+    }
+  }
+  for (int s = 0; s < n_steps; ++s) {
+    rc = direct_step(h, dt);
+    if (rc) return rc;
+  }
+  return warn;
+}
+
+int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
+  if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
+  if (value != 0 && value != 1) return fail(RIDG_E_INVAL, "option values are 0 or 1");
+  int err = hipStreamSynchronize(h->stream);
+  if (err) return hip_fail(err, "hipStreamSynchronize");
+  switch (option) {
+    case RIDG_OPT_GRAPH:
+      h->opt_graph = (int)value;
+      break;
+    case RIDG_OPT_PLAN_LAYOUT:
+      if (h->P.solver != RIDG_SOLVER_REGION && value) return fail(RIDG_E_UNSUPPORTED, "plan layout applies to REGION");
+      h->opt_layout = (int)value;
+      break;
+    case RIDG_OPT_FUSED:
+      if (value && (h->P.solver != RIDG_SOLVER_PREFACTORED || !fused_fits(h->P.d, h->P.M, h->P.nel)))
+        return fail(RIDG_E_UNSUPPORTED, "fused steps need the PREFACTORED solver and a mesh that fits in LDS");
+      h->opt_fused = (int)value;
+      break;
+    default:
+      return fail(RIDG_E_INVAL, "unknown option");
+  }
+  drop_graphs(h);
+  return RIDG_OK;
+}
+
+int ridg_get_option(ridg_t* h, int32_t option, int64_t* value) {
+  if (!h || !value) return fail(RIDG_E_INVAL, "NULL argument");
+  switch (option) {
+    case RIDG_OPT_GRAPH: *value = h->opt_graph; return RIDG_OK;
+    case RIDG_OPT_PLAN_LAYOUT: *value = h->opt_layout; return RIDG_OK;
+    case RIDG_OPT_FUSED: *value = h->opt_fused; return RIDG_OK;
+    default: return fail(RIDG_E_INVAL, "unknown option");
+  }
+}
+
+
+int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step) {
+  if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
+  if (steps < 2 || steps > 100000) return fail(RIDG_E_INVAL, "steps must be in 2..100000");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be positive and finite");
+  if (h->timing) return fail(RIDG_E_INVAL, "switch stage timing off before autotuning");
+  const std::string key = tune_key(h, steps);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_file_load();
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      h->opt_graph = it->second[0];
+      h->opt_layout = it->second[1];
+      h->opt_fused = it->second[2];
+      drop_graphs(h);
+      if (best_ms_per_step) *best_ms_per_step = -1.0;  // from the cache, not re-measured
+      return RIDG_OK;
+    }
+  }
+  std::vector<std::array<int, 3>> cands;
+  const bool region = h->P.solver == RIDG_SOLVER_REGION;
+  const bool fusable = h->P.solver == RIDG_SOLVER_PREFACTORED && fused_fits(h->P.d, h->P.M, h->P.nel);
+  for (int g = 0; g < 2; ++g)
+    for (int l = 0; l < (region ? 2 : 1); ++l) cands.push_back({g, l, 0});
+  if (fusable) cands.push_back({0, 0, 1});
+  // keep the state: tuning steps run on a copy that is restored afterwards
+  const size_t bytes = (size_t)h->P.nel * h->T.ns * 8;
+  const int cur0 = h->cur;
+  int err = hipMemcpyAsync(h->stage, h->Q[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (!err) err = hipEventCreate(&e0);
+  if (!err) err = hipEventCreate(&e1);
+  double best = 1e300;
+  std::array<int, 3> pick = {h->opt_graph, h->opt_layout, h->opt_fused};
+  int rc = RIDG_OK;
+  for (size_t c = 0; c < cands.size() && !err && !rc; ++c) {
+    h->opt_graph = cands[c][0];
+    h->opt_layout = cands[c][1];
+    h->opt_fused = cands[c][2];
+    drop_graphs(h);
+    rc = ridg_step(h, 2, dt);  // warm-up (and graph capture)
+    if (rc < 0) break;
+    rc = RIDG_OK;
+    err = hipEventRecord(e0, h->stream);
+    if (!err) rc = ridg_step(h, steps, dt);
+    if (rc < 0) break;
+    rc = RIDG_OK;
+    if (!err) err = hipEventRecord(e1, h->stream);
+    if (!err) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (!err) err = hipEventElapsedTime(&ms, e0, e1);
+    if (!err && ms / steps < best) {
+      best = ms / steps;
+      pick = cands[c];
+    }
+    if (!err) err = hipMemcpyAsync(h->Q[cur0], h->stage, bytes, hipMemcpyDeviceToDevice, h->stream);
+    h->cur = cur0;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->opt_graph = pick[0];
+  h->opt_layout = pick[1];
+  h->opt_fused = pick[2];
+  drop_graphs(h);
+  if (rc < 0) return rc;
+  if (err) return hip_fail(err, "autotune");
+  err = hipStreamSynchronize(h->stream);
+  if (err) return hip_fail(err, "autotune");
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[key] = pick;
+    tune_file_append(key, pick);
+  }
+  if (best_ms_per_step) *best_ms_per_step = best;
+  return RIDG_OK;
 }
 
 int ridg_get_prediction(ridg_t* h, double dt, double* w, size_t count, int32_t where) {

@@ -96,21 +96,11 @@ __global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt
   if (write) W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
 }
 
-// Segment layout of the plan kernel: packed theta_T-lane segments (default) or power-of-two
-// segments with DPP reductions (RIDG_PLAN_PADDED=1), chosen once per process.
-static bool plan_padded() {
-  static bool v = [] {
-    const char* e = getenv("RIDG_PLAN_PADDED");
-    return e && atoi(e) == 1;
-  }();
-  return v;
-}
-
 template <int D, int M>
 struct IpwL {
-  static int run() { return plan_padded() ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S; }
+  static int run(int layout) { return layout ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S; }
 };
-int items_per_wave(int d, int M) { return dispatch_dm<IpwL>(d, M); }
+int items_per_wave(int d, int M, int layout) { return dispatch_dm<IpwL>(d, M, layout); }
 
 template <int D, int M, bool PADDED>
 static int launch_plans(int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
@@ -131,20 +121,21 @@ static int launch_plans(int precision, int refine, const DevGeom& g, double dt, 
 
 template <int D, int M>
 struct PlansL {
-  static int run(int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
+  static int run(int layout, int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
                  const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
-    if (plan_padded())
+    if (layout)
       return launch_plans<D, M, true>(precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
     return launch_plans<D, M, false>(precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
   }
 };
 
-int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom& g, double dt, const double* Q,
-                         double* W, const PlanTables& t, const PlanRec* plans, const int32_t* items,
+int launch_predict_plans(int d, int M, int layout, int precision, int refine, const DevGeom& g, double dt,
+                         const double* Q, double* W, const PlanTables& t, const PlanRec* plans, const int32_t* items,
                          const int32_t* item_plan, int64_t n_items, void* stream) {
-  return dispatch_dm<PlansL>(d, M, precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+  return dispatch_dm<PlansL>(d, M, layout, precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items,
+                             stream);
 }
 
 

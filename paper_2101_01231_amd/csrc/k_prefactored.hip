@@ -1,50 +1,61 @@
-// Constant-velocity prediction with the host-prefactored operator G (Sec. 2.2, one linear solve).
+// Constant-velocity prediction with the host-prefactored operator G (Sec. 2.2, one linear solve),
+// and the fused small-mesh kernel that runs whole RIDG steps (prediction, then correction, Sec.
+// 2.3) on one workgroup with the mesh state resident in LDS.
 #include "kernels_common.hpp"
 
 namespace ridg {
-
-// ---------------------------------------------------------------- prefactored prediction
-// Constant velocity: W_e = sum_tap G_tap Q_{e + off_tap} (Sec. 2.2 system solved once on the host).
-struct Taps {
-  int8_t off[kMaxBlocks][3];
-};
 
 template <int D, int M>
 __global__ __launch_bounds__(256) void predict_prefactored_kernel(DevGeom g, const double* __restrict__ Q,
                                                                   double* __restrict__ W,
                                                                   const double* __restrict__ G, Taps taps,
                                                                   int ntaps) {
-  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nel) return;
-  int idx[3];
-  elem_idx(g, e, idx);
-  double w[NT];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) w[k] = 0.0;
-  for (int t = 0; t < ntaps; ++t) {
-    const int64_t src = elem_lin(g, idx[0] + taps.off[t][0], idx[1] + taps.off[t][1], idx[2] + taps.off[t][2]);
-    double q[NS];
-#pragma unroll
-    for (int l = 0; l < NS; ++l) q[l] = Q[(int64_t)l * nel + src];
-    const double* Gt = G + (size_t)t * NT * NS;
-#pragma unroll
-    for (int k = 0; k < NT; ++k)
-#pragma unroll
-      for (int l = 0; l < NS; ++l) w[k] = fma(Gt[k * NS + l], q[l], w[k]);
+  predict_prefactored_elem<D, M>(g, Q, W, G, taps, ntaps, e, nel);
+}
+
+// n_steps full steps with a workgroup-wide barrier between the prediction of every element and
+// the correction (which reads the face neighbours' predictions). Q and W live in LDS; the
+// correction updates Q in place (each element writes only its own coefficients).
+constexpr int kFusedThreads = 1024;
+constexpr int64_t kFusedLdsBytes = 160 * 1024;
+
+template <int D, int M>
+__global__ __launch_bounds__(kFusedThreads) void fused_prefactored_kernel(DevGeom g, double dt,
+                                                                         const double* __restrict__ Qin,
+                                                                         double* __restrict__ Qout,
+                                                                         const double* __restrict__ G, Taps taps,
+                                                                         int ntaps, DevTensors t, int n_steps) {
+  constexpr int NS = n_space(D, M);
+  extern __shared__ double sm[];
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  double* sQ = sm;
+  double* sW = sm + (size_t)NS * nel;
+  for (int64_t q = threadIdx.x; q < (int64_t)NS * nel; q += blockDim.x) sQ[q] = Qin[q];
+  __syncthreads();
+  for (int s = 0; s < n_steps; ++s) {
+    for (int64_t e = threadIdx.x; e < nel; e += blockDim.x) predict_prefactored_elem<D, M>(g, sQ, sW, G, taps, ntaps, e, nel);
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < nel; e += blockDim.x) correct_elem<D, M, false>(g, dt, sQ, sW, sQ, t, e, nel);
+    __syncthreads();
   }
-#pragma unroll
-  for (int k = 0; k < NT; ++k) W[(int64_t)k * nel + e] = w[k];
+  for (int64_t q = threadIdx.x; q < (int64_t)NS * nel; q += blockDim.x) Qout[q] = sQ[q];
+}
+
+static Taps make_taps(const int32_t* taps, int ntaps) {
+  Taps tp;
+  for (int t = 0; t < kMaxBlocks; ++t)
+    for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+  return tp;
 }
 
 template <int D, int M>
 struct PrefactoredL {
   static int run(const DevGeom& g, const double* Q, double* W, const double* G, const int32_t* taps, int ntaps,
                  void* stream) {
-    Taps tp;
-    for (int t = 0; t < kMaxBlocks; ++t)
-      for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+    const Taps tp = make_taps(taps, ntaps);
     const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
     hipLaunchKernelGGL((predict_prefactored_kernel<D, M>), dim3(grid_for(nel, 256)), dim3(256), 0,
                        (hipStream_t)stream, g, Q, W, G, tp, ntaps);
@@ -57,5 +68,38 @@ int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, 
   return dispatch_dm<PrefactoredL>(d, M, g, Q, W, G, taps, ntaps, stream);
 }
 
+template <int D, int M>
+struct FusedFitsL {
+  static int run(int64_t nel) {
+    return (int64_t)(n_space(D, M) + n_spacetime(D, M)) * 8 * nel <= kFusedLdsBytes ? 1 : 0;
+  }
+};
+
+int fused_fits(int d, int M, int64_t nel) { return dispatch_dm<FusedFitsL>(d, M, nel); }
+
+template <int D, int M>
+struct FusedL {
+  static int run(const DevGeom& g, double dt, const double* Qin, double* Qout, const double* G, const int32_t* taps,
+                 int ntaps, const DevTensors& t, int n_steps, void* stream) {
+    const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+    const int64_t bytes = (int64_t)(n_space(D, M) + n_spacetime(D, M)) * 8 * nel;
+    if (bytes > kFusedLdsBytes) return (int)hipErrorInvalidValue;
+    static bool attr = [] {
+      return hipFuncSetAttribute((const void*)fused_prefactored_kernel<D, M>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLdsBytes) == hipSuccess;
+    }();
+    if (!attr && bytes > 64 * 1024) return (int)hipErrorInvalidValue;
+    const Taps tp = make_taps(taps, ntaps);
+    hipLaunchKernelGGL((fused_prefactored_kernel<D, M>), dim3(1), dim3(kFusedThreads), (size_t)bytes,
+                       (hipStream_t)stream, g, dt, Qin, Qout, G, tp, ntaps, t, n_steps);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_fused_prefactored(int d, int M, const DevGeom& g, double dt, const double* Qin, double* Qout,
+                             const double* G, const int32_t* taps, int ntaps, const DevTensors& t, int n_steps,
+                             void* stream) {
+  return dispatch_dm<FusedL>(d, M, g, dt, Qin, Qout, G, taps, ntaps, t, n_steps, stream);
+}
 
 }  // namespace ridg

@@ -284,4 +284,103 @@ static int dispatch_dm(int d, int M, Args... args) {
 
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
+// ---------------------------------------------------------------- correction (per element)
+// Q'_e = Q_e + 2^-d [ sum_i sum_p V_ip Cv_ip W_e - sum_faces sum_p V_ip (CFo W_e | CFn W_nbr) ]
+template <int D, int M, bool AFFINE>
+__device__ inline void correct_elem(const DevGeom& g, double dt, const double* Q, const double* W, double* Qout,
+                                    const DevTensors& t, int64_t e, int64_t nel) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NP = D + 1;
+  int idx[3];
+  elem_idx(g, e, idx);
+  double V[D][D + 1];
+  vel_modes<D>(g, idx, dt, V);
+  double we[NT], acc[NS];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) we[l] = W[(int64_t)l * nel + e];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+#pragma unroll 1
+  for (int i = 0; i < D; ++i) {
+#pragma unroll 1
+    for (int p = 0; p < NP; ++p) {
+      if (p == 1 + i || (!AFFINE && p > 0)) continue;
+      const double vp = V[i][p];
+      const double* cv = t.Cv + ((size_t)i * NP + p) * NS * NT;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) s = fma(cv[k * NT + l], we[l], s);
+        acc[k] = fma(vp, s, acc[k]);
+      }
+    }
+#pragma unroll 1
+    for (int sd = 0; sd < 2; ++sd) {
+      const int s = sd ? 1 : -1;
+      const int side = face_side<D>(g, idx, i, s);
+      double wn[NT];
+      const double* tens;
+      if (side == 0) {
+#pragma unroll
+        for (int l = 0; l < NT; ++l) wn[l] = we[l];
+        tens = t.CFo;
+      } else {
+        int j[3] = {idx[0], idx[1], idx[2]};
+        j[i] += s;
+        const int64_t en = elem_lin(g, j[0], j[1], j[2]);
+#pragma unroll
+        for (int l = 0; l < NT; ++l) wn[l] = W[(int64_t)l * nel + en];
+        tens = t.CFn;
+      }
+#pragma unroll 1
+      for (int p = 0; p < NP; ++p) {
+        if (p == 1 + i || (!AFFINE && p > 0)) continue;
+        const double vp = V[i][p];
+        const double* cf = tens + (((size_t)i * 2 + sd) * NP + p) * NS * NT;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+          double s2 = 0.0;
+#pragma unroll
+          for (int l = 0; l < NT; ++l) s2 = fma(cf[k * NT + l], wn[l], s2);
+          acc[k] = fma(-vp, s2, acc[k]);
+        }
+      }
+    }
+  }
+  constexpr double scale = 1.0 / (double)(1 << D);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Qout[(int64_t)k * nel + e] = fma(acc[k], scale, Q[(int64_t)k * nel + e]);
+}
+
+
+
+// Constant velocity: W_e = sum_tap G_tap Q_{e + off_tap} (the Sec. 2.2 system solved once on the host).
+struct Taps {
+  int8_t off[kMaxBlocks][3];
+};
+
+template <int D, int M>
+__device__ inline void predict_prefactored_elem(const DevGeom& g, const double* Q, double* W, const double* G,
+                                                const Taps& taps, int ntaps, int64_t e, int64_t nel) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
+  int idx[3];
+  elem_idx(g, e, idx);
+  double w[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) w[k] = 0.0;
+  for (int tp = 0; tp < ntaps; ++tp) {
+    const int64_t src = elem_lin(g, idx[0] + taps.off[tp][0], idx[1] + taps.off[tp][1], idx[2] + taps.off[tp][2]);
+    double q[NS];
+#pragma unroll
+    for (int l = 0; l < NS; ++l) q[l] = Q[(int64_t)l * nel + src];
+    const double* Gt = G + (size_t)tp * NT * NS;
+#pragma unroll
+    for (int k = 0; k < NT; ++k)
+#pragma unroll
+      for (int l = 0; l < NS; ++l) w[k] = fma(Gt[k * NS + l], q[l], w[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < NT; ++k) W[(int64_t)k * nel + e] = w[k];
+}
+
 }  // namespace ridg

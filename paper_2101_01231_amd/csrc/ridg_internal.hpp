@@ -178,10 +178,17 @@ int launch_aos_to_soa(const double* src, double* dst, int64_t nel, int nmodes, v
 int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
 int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, double* W,
                                const double* G, const int32_t* taps, int ntaps, void* stream);
-int launch_predict_plans(int d, int M, int precision, int refine, const DevGeom& g, double dt,
+// layout: 0 = packed theta_T-lane segments, 1 = power-of-two segments (DPP reductions)
+int launch_predict_plans(int d, int M, int layout, int precision, int refine, const DevGeom& g, double dt,
                          const double* Q, double* W, const PlanTables& t, const PlanRec* plans,
                          const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
-int items_per_wave(int d, int M);  // work-list padding multiple (items a wavefront takes at once)
+int items_per_wave(int d, int M, int layout);  // work-list padding multiple (regions a wavefront takes at once)
+// Whole run of n_steps on one workgroup (mesh state resident in LDS), constant velocity;
+// returns hipErrorInvalidValue when the mesh does not fit.
+int fused_fits(int d, int M, int64_t nel);
+int launch_fused_prefactored(int d, int M, const DevGeom& g, double dt, const double* Qin, double* Qout,
+                             const double* G, const int32_t* taps, int ntaps, const DevTensors& t, int n_steps,
+                             void* stream);
 int launch_predict_tear(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
                         const PlanTables& t, const PlanRec* plans, const int32_t* elems, int64_t n_elems,
                         void* stream);

@@ -28,11 +28,12 @@ FLUX_CONST, FLUX_ROTATION, FLUX_AFFINE = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
+OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED = 1, 2, 3
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
-    "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_synchronize",
-    "ridg_destroy",
+    "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_set_option",
+    "ridg_get_option", "ridg_autotune", "ridg_synchronize", "ridg_destroy",
     "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_error_string", "ridg_last_error",
 ]
 
@@ -107,6 +108,9 @@ def lib():
         L.ridg_get_info.argtypes = [vp, ctypes.POINTER(RidgInfo)]
         L.ridg_enable_timing.argtypes = [vp, i32]
         L.ridg_get_timing.argtypes = [vp, ctypes.POINTER(RidgTiming)]
+        L.ridg_set_option.argtypes = [vp, i32, i64]
+        L.ridg_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
+        L.ridg_autotune.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
         L.ridg_synchronize.argtypes = [vp]
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
@@ -244,6 +248,20 @@ class Simulation:
         t = RidgTiming()
         _check(lib().ridg_get_timing(self.handle, ctypes.byref(t)))
         return t
+
+    def set_option(self, option, value):
+        _check(lib().ridg_set_option(self.handle, int(option), int(value)))
+
+    def get_option(self, option):
+        v = ctypes.c_int64()
+        _check(lib().ridg_get_option(self.handle, int(option), ctypes.byref(v)))
+        return v.value
+
+    def autotune(self, dt, steps=10):
+        """Pick the fastest option set for this problem; returns ms per step (-1 if cached)."""
+        out = ctypes.c_double()
+        _check(lib().ridg_autotune(self.handle, float(dt), int(steps), ctypes.byref(out)))
+        return out.value
 
     def synchronize(self):
         _check(lib().ridg_synchronize(self.handle))
