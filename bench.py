@@ -130,6 +130,33 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
                 value=info.n_elements * info.theta_t * steps / wall)
 
 
+def serving(args):
+    """Serving mix: Poisson arrivals (mean 20/s) of independent periodic advection runs, 60% 2D /
+    30% 1D / 10% 3D, orders 1..5, 50..500 steps each, continuously batched on one GPU."""
+    from paper_2101_01231_amd import inputs, serve
+
+    reqs = serve.requests_from_mix(inputs.serving_requests(args.requests))
+    for r in reqs:
+        r.initial_state()  # inputs prepared before the clock starts
+    srv = serve.Server(mem_budget_bytes=int(args.mem_gb * (1 << 30)))
+    print(f"[bench] serving {len(reqs)} requests, time scale {args.time_scale}", file=sys.stderr, flush=True)
+    st = srv.run(reqs, time_scale=args.time_scale, keep_results=False)
+    out = {
+        "metric": "space-time DOF-updates/s (serving mix); p99 per-step latency",
+        "value": st["st_dof_updates_per_s_busy"],
+        "unit": "ST-DOF-updates/s",
+        "n_gpus": 1, "steps": st["ticks"], "warmup": 0,
+        "ms_per_step": st["busy_s"] * 1e3 / max(st["ticks"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "serving-mix", "requests": len(reqs), "arrival_rate_per_s": 20 * args.time_scale,
+                   "mem_budget_gb": args.mem_gb},
+        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
+        "wall_s": st["wall_s"], "busy_s": st["busy_s"], "mean_active": st["mean_active"],
+        "st_dof_updates_per_s_wall": st["st_dof_updates_per_s_wall"], "rejected": len(st["rejected"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +169,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
+    ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
+    ap.add_argument("--time-scale", type=float, default=1.0, help="serving: arrival clock speed-up")
+    ap.add_argument("--mem-gb", type=float, default=64.0, help="serving: device memory budget")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
@@ -149,6 +179,8 @@ def main():
         sys.exit(2)
     from paper_2101_01231_amd import ridg
 
+    if args.workload == "serving":
+        return serving(args)
     wl = workload(args.workload)
     has_fp32 = wl.velocity[0] != "const" or args.solver == "region"
     want = ["fp64", "fp32"] if (args.precision == "best" and has_fp32) else \

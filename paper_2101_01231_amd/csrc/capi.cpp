@@ -737,6 +737,70 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
   return warn;
 }
 
+int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, int32_t n_steps, void* hip_stream) {
+  if (count < 0 || n_steps < 0) return fail(RIDG_E_INVAL, "count and n_steps must be >= 0");
+  if (count == 0 || n_steps == 0) return RIDG_OK;
+  if (!handles || !dts) return fail(RIDG_E_INVAL, "NULL argument");
+  for (int i = 0; i < count; ++i) {
+    ridg_t* h = handles[i];
+    if (!h) return fail(RIDG_E_INVAL, "NULL handle in the batch");
+    if (h->P.solver != RIDG_SOLVER_PREFACTORED) return fail(RIDG_E_UNSUPPORTED, "batched steps need PREFACTORED handles");
+    if (!(dts[i] > 0.0) || !std::isfinite(dts[i])) return fail(RIDG_E_INVAL, "dt must be positive and finite");
+    for (int j = 0; j < i; ++j)
+      if (handles[j] == h) return fail(RIDG_E_INVAL, "a handle appears twice in the batch");
+  }
+  for (int i = 0; i < count; ++i) {
+    int rc = ensure_dt_tables(handles[i], dts[i]);
+    if (rc) return rc;
+    if (handles[i]->ntaps > kBatchTaps) return fail(RIDG_E_UNSUPPORTED, "more than 8 taps");
+  }
+  // families: same (dim, order)
+  std::vector<std::vector<int>> fam;
+  for (int i = 0; i < count; ++i) {
+    bool placed = false;
+    for (auto& f : fam)
+      if (handles[f[0]]->P.d == handles[i]->P.d && handles[f[0]]->P.M == handles[i]->P.M) {
+        f.push_back(i);
+        placed = true;
+        break;
+      }
+    if (!placed) fam.push_back({i});
+  }
+  for (int s = 0; s < n_steps; ++s) {
+    for (auto& f : fam) {
+      const ridg_t* h0 = handles[f[0]];
+      for (size_t c0 = 0; c0 < f.size(); c0 += kBatchMax) {
+        BatchArgs args{};
+        int64_t blk = 0;
+        for (size_t c = c0; c < f.size() && c < c0 + kBatchMax; ++c) {
+          ridg_t* h = handles[f[c]];
+          BatchDesc& d = args.d[args.count++];
+          d.Qin = h->Q[h->cur];
+          d.Qout = h->Q[1 - h->cur];
+          d.W = h->W;
+          d.G = h->G;
+          d.block_begin = blk;
+          d.nel = h->P.nel;
+          for (int i = 0; i < 3; ++i) {
+            d.h[i] = h->P.h[i];
+            d.v[i] = h->P.vel.a[i];
+            d.n[i] = h->P.n[i];
+          }
+          d.dt = dts[f[c]];
+          d.ntaps = h->ntaps;
+          for (int t = 0; t < h->ntaps; ++t)
+            for (int i = 0; i < 3; ++i) d.taps[t][i] = (int8_t)h->host_taps[3 * t + i];
+          blk += (h->P.nel + 255) / 256;
+        }
+        int err = launch_batch_step(h0->P.d, h0->P.M, args, h0->dt, hip_stream);
+        if (err) return hip_fail(err, "batched step launch");
+      }
+    }
+    for (int i = 0; i < count; ++i) handles[i]->cur ^= 1;
+  }
+  return RIDG_OK;
+}
+
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
   if (value != 0 && value != 1) return fail(RIDG_E_INVAL, "option values are 0 or 1");

@@ -173,7 +173,32 @@ struct DevGeom {
   double g[3][3];
 };
 
-// Launchers (defined in kernels.hip). All return a hipError_t as int.
+// Serving: per-problem descriptors passed by value to the shared launches (k_batch.hip).
+constexpr int kBatchTaps = 8;  // constant velocity: the upwind cone has at most 2^d taps
+constexpr int kBatchMax = 16;  // problems per launch (kernel-argument budget)
+struct BatchDesc {
+  const double* Qin;
+  double* Qout;
+  double* W;
+  const double* G;
+  int64_t block_begin;  // first workgroup of this problem in the launch grid
+  int64_t nel;
+  double h[3];
+  double v[3];
+  double dt;
+  int32_t n[3];
+  int32_t ntaps;
+  int8_t taps[kBatchTaps][3];
+  int8_t pad[8];
+};
+struct BatchArgs {
+  BatchDesc d[kBatchMax];
+  int32_t count;
+  int32_t pad;
+};
+int launch_batch_step(int d, int M, const BatchArgs& args, const DevTensors& t, void* stream);
+
+// Launchers (defined in the k_*.hip units). All return a hipError_t as int.
 int launch_aos_to_soa(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
 int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
 int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, double* W,

@@ -33,7 +33,7 @@ OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED = 1, 2, 3
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
     "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_set_option",
-    "ridg_get_option", "ridg_autotune", "ridg_synchronize", "ridg_destroy",
+    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_synchronize", "ridg_destroy",
     "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_error_string", "ridg_last_error",
 ]
 
@@ -111,6 +111,7 @@ def lib():
         L.ridg_set_option.argtypes = [vp, i32, i64]
         L.ridg_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.ridg_autotune.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
+        L.ridg_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), i32, vp]
         L.ridg_synchronize.argtypes = [vp]
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
@@ -178,6 +179,14 @@ def host_prediction_operator(problem, dt):
     G = np.empty((nt, 3 ** d * ns))
     _check(lib().ridg_host_prediction_operator(ctypes.byref(problem), dt, G.ctypes.data, G.size))
     return G
+
+
+def step_batch(sims, dts, n_steps, stream):
+    """Advance several PREFACTORED simulations in shared launches on `stream` (a torch stream)."""
+    n = len(sims)
+    hs = (ctypes.c_void_p * n)(*[s.handle.value for s in sims])
+    d = (ctypes.c_double * n)(*[float(x) for x in dts])
+    return _check(lib().ridg_step_batch(hs, n, d, int(n_steps), ctypes.c_void_p(stream.cuda_stream)))
 
 
 class Simulation:

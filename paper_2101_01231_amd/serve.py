@@ -1,0 +1,155 @@
+"""Continuous-batching server for independent RIDG runs on one GPU.
+
+Requests (independent periodic constant-velocity advection problems of any dimension, mesh size and
+order, each with its own number of steps and step size) arrive over time. The server
+
+  * admits a request as soon as it has arrived and its device footprint (libridg workspace) fits
+    the memory budget, creating its handle and uploading its initial state;
+  * keeps every admitted request's state resident on the device;
+  * on each tick advances all active requests by one step with shared launches
+    (`ridg_step_batch`: one prediction and one correction launch per (dimension, order) family);
+  * retires finished requests (state copied back, workspace freed) and admits waiting ones.
+
+Per-step latency is measured with HIP events on the server's stream (a step becomes eligible when
+its tick starts and completes when the tick's launches finish). A request that cannot be served
+(invalid, or larger than the whole budget) is rejected alone; the others continue.
+"""
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import inputs, ridg
+
+
+@dataclass
+class Request:
+    id: int
+    arrival: float
+    d: int
+    n: tuple
+    M: int
+    steps: int
+    velocity: tuple
+    dt: float
+    seed: int
+    q0: np.ndarray = field(default=None, repr=False)
+
+    def problem(self):
+        return ridg.make_problem(self.d, self.n, self.M, velocity=self.velocity)
+
+    def initial_state(self):
+        if self.q0 is None:
+            self.q0 = inputs.gaussian_bump_state(self.d, self.n, self.M, self.seed)
+        return self.q0
+
+    @property
+    def st_dofs_per_step(self):
+        from math import comb
+        return int(np.prod(self.n)) * comb(self.M + self.d, self.d + 1)
+
+
+def requests_from_mix(specs):
+    return [Request(s["id"], s["arrival"], s["d"], tuple(s["n"]), s["M"], s["steps"], tuple(s["velocity"]),
+                    s["dt"], s["seed"]) for s in specs]
+
+
+class Server:
+    def __init__(self, device="cuda:0", mem_budget_bytes=32 << 30, max_active=256):
+        import torch
+
+        self.torch = torch
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(self.device)  # default priority
+        self.budget = int(mem_budget_bytes)
+        self.max_active = max_active
+        self.used = 0
+
+    def _admit(self, req):
+        prob = req.problem()
+        need = ridg.workspace_bytes(prob)
+        if need > self.budget:
+            raise ridg.RidgError(ridg.RIDG_E_NOMEM, f"request {req.id} needs {need} bytes, budget {self.budget}")
+        if self.used + need > self.budget:
+            return None
+        sim = ridg.Simulation(prob, device=self.device, stream=self.stream)
+        sim.set_state(req.initial_state())
+        self.used += need
+        return dict(req=req, sim=sim, bytes=need, done=0, admitted=time.perf_counter())
+
+    def run(self, requests, time_scale=1.0, keep_results=True):
+        """Serve the requests (arrival times in seconds, divided by time_scale); returns stats."""
+        torch = self.torch
+        pending = deque(sorted(requests, key=lambda r: r.arrival))
+        waiting = deque()
+        active = []
+        results, rejected = {}, {}
+        lat_ms, tick_ms, active_counts = [], [], []
+        st_updates = 0
+        t0 = time.perf_counter()
+        busy = 0.0
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        while pending or waiting or active:
+            now = (time.perf_counter() - t0) * time_scale
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            while waiting and len(active) < self.max_active:
+                try:
+                    slot = self._admit(waiting[0])
+                except ridg.RidgError as err:
+                    rejected[waiting.popleft().id] = str(err)
+                    continue
+                if slot is None:
+                    break
+                waiting.popleft()
+                active.append(slot)
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, (pending[0].arrival - now) / time_scale))
+                continue
+            sims = [a["sim"] for a in active]
+            dts = [a["req"].dt for a in active]
+            tb = time.perf_counter()
+            ev0.record(self.stream)
+            ridg.step_batch(sims, dts, 1, self.stream)
+            ev1.record(self.stream)
+            ev1.synchronize()
+            busy += time.perf_counter() - tb
+            ms = ev0.elapsed_time(ev1)
+            tick_ms.append(ms)
+            active_counts.append(len(active))
+            lat_ms.extend([ms] * len(active))
+            still = []
+            for a in active:
+                a["done"] += 1
+                st_updates += a["req"].st_dofs_per_step
+                if a["done"] >= a["req"].steps:
+                    q = a["sim"].get_state()
+                    if keep_results:
+                        results[a["req"].id] = q
+                    a["sim"].close()
+                    self.used -= a["bytes"]
+                else:
+                    still.append(a)
+            active = still
+        wall = time.perf_counter() - t0
+        lat = np.array(lat_ms) if lat_ms else np.zeros(1)
+        return dict(results=results, rejected=rejected, wall_s=wall, busy_s=busy, ticks=len(tick_ms),
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    mean_active=float(np.mean(active_counts)) if active_counts else 0.0,
+                    st_dof_updates=st_updates,
+                    st_dof_updates_per_s_busy=st_updates / busy if busy else 0.0,
+                    st_dof_updates_per_s_wall=st_updates / wall if wall else 0.0)
+
+
+def run_alone(req, device="cuda:0"):
+    """The same request advanced on its own handle with ridg_step (reference for the mix)."""
+    sim = ridg.Simulation(req.problem(), device=device)
+    sim.set_state(req.initial_state())
+    sim.step(req.steps, req.dt)
+    out = sim.get_state()
+    sim.close()
+    return out

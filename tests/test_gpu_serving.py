@@ -1,0 +1,59 @@
+"""GPU: the serving row - continuous batching of independent runs with shared launches.
+
+Each request's result in the mix must equal (bitwise) the same request advanced alone with
+ridg_step: the batched kernels run the same per-element arithmetic."""
+
+import numpy as np
+import pytest
+
+from paper_2101_01231_amd import ridg, serve
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    specs = [
+        dict(id=0, arrival=0.00, d=1, n=(200,), M=3, steps=40, velocity=(0.7,), seed=1),
+        dict(id=1, arrival=0.00, d=2, n=(48, 40), M=4, steps=25, velocity=(-0.5, 0.3), seed=2),
+        dict(id=2, arrival=0.01, d=3, n=(12, 10, 9), M=3, steps=30, velocity=(0.4, -0.9, 0.2), seed=3),
+        dict(id=3, arrival=0.02, d=2, n=(33, 33), M=4, steps=35, velocity=(0.8, 0.1), seed=4),
+        dict(id=4, arrival=0.03, d=1, n=(64,), M=5, steps=50, velocity=(-1.0,), seed=5),
+        dict(id=5, arrival=0.05, d=2, n=(20, 64), M=1, steps=20, velocity=(0.2, 0.6), seed=6),
+        dict(id=6, arrival=0.08, d=3, n=(8, 8, 8), M=5, steps=15, velocity=(0.5, 0.5, -0.5), seed=7),
+        dict(id=7, arrival=0.10, d=2, n=(40, 40), M=2, steps=60, velocity=(0.0, -0.7), seed=8),
+    ]
+    for s in specs:
+        s["dt"] = 0.5 / (max(s["n"]) * max(abs(v) for v in s["velocity"]))
+    return serve.requests_from_mix(specs)
+
+
+def test_alone_equals_in_mix():
+    reqs = _mix()
+    srv = serve.Server()
+    stats = srv.run(reqs, time_scale=1.0)
+    print(f"[serve] ticks={stats['ticks']} mean_active={stats['mean_active']:.2f} p99={stats['p99_ms']:.3f} ms",
+          flush=True)
+    assert not stats["rejected"]
+    assert stats["mean_active"] > 1.0  # requests overlapped on the device
+    for r in reqs:
+        alone = serve.run_alone(r)
+        assert np.array_equal(stats["results"][r.id], alone), r.id
+
+
+def test_failed_request_is_isolated():
+    reqs = _mix()[:3]
+    bad = serve.Request(99, 0.0, 2, (2, 2), 3, 5, (1.0, 1.0), 0.1, 0)  # n < 3: rejected by the library
+    huge = serve.Request(98, 0.0, 3, (96, 96, 96), 5, 5, (1.0, 1.0, 1.0), 0.001, 0)
+    srv = serve.Server(mem_budget_bytes=256 << 20)  # the 96^3 order-5 request can never fit
+    stats = srv.run(reqs + [bad, huge], time_scale=1.0)
+    assert set(stats["rejected"]) == {98, 99}
+    for r in reqs:
+        assert np.array_equal(stats["results"][r.id], serve.run_alone(r))
+
+
+def test_step_batch_rejects_non_prefactored_handles():
+    import torch
+    rot = ridg.Simulation(ridg.make_problem(2, (16, 16), 3, flux=ridg.FLUX_ROTATION))
+    with pytest.raises(ridg.RidgError):
+        ridg.step_batch([rot], [0.01], 1, torch.cuda.current_stream())
+    rot.close()
