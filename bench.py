@@ -100,6 +100,15 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     sim = ridg.Simulation(prob, device="cuda:0")
     info = sim.info
     sim.set_state(wl.q0)
+    # autotuner (native, HIP events): picks segment layout / composite stencil / fused steps; graph
+    # replay is then switched off so that the library's per-stage events cover the timed steps
+    sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
+    sim.set_option(ridg.OPT_GRAPH, 0)
+    opts = {"plan_layout": sim.get_option(ridg.OPT_PLAN_LAYOUT), "composite": sim.get_option(ridg.OPT_COMPOSITE),
+            "fused": sim.get_option(ridg.OPT_FUSED)}
+    if opts["fused"]:
+        sim.set_option(ridg.OPT_FUSED, 0)  # one launch for all steps would hide the per-step latency
+        opts["fused"] = 0
     print(f"[bench] {label}: {wl.name} n={wl.n} M={wl.M} solver={info.solver} plans={info.n_plans} "
           f"tear={info.n_tear_elements} dense={info.n_dense_elements} warmup={warmup} steps={steps}",
           file=sys.stderr, flush=True)
@@ -126,8 +135,27 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     sim.close()
     pred_ms = tim.predict_ms / max(tim.steps, 1)
     corr_ms = tim.correct_ms / max(tim.steps, 1)
-    return dict(info=info, wall=wall, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q,
+    return dict(info=info, wall=wall, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q, opts=opts,
                 value=info.n_elements * info.theta_t * steps / wall)
+
+
+def copy_reference(args):
+    """A plain elementwise device copy of known size (reads N bytes, writes N bytes), used to
+    calibrate the HBM byte counters (FETCH_SIZE / WRITE_SIZE) of the profiler."""
+    import torch
+    n = 256 << 20  # bytes
+    x = torch.ones(n // 8, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(args.warmup):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    print(json.dumps({"metric": "copy bandwidth (calibration)", "value": 2 * n / dt / 1e9, "unit": "GB/s",
+                      "bytes_read_per_launch": n, "bytes_written_per_launch": n, "steps": args.steps}), flush=True)
 
 
 def serving(args):
@@ -181,6 +209,8 @@ def main():
 
     if args.workload == "serving":
         return serving(args)
+    if args.workload == "copy":
+        return copy_reference(args)
     wl = workload(args.workload)
     has_fp32 = wl.velocity[0] != "const" or args.solver == "region"
     want = ["fp64", "fp32"] if (args.precision == "best" and has_fp32) else \
@@ -209,9 +239,21 @@ def main():
                                "achieved_gbs": info.bytes_correct / (R["corr_ms"] * 1e-3) / 1e9,
                                "avg_ms": R["corr_ms"]}}
     if info.solver == ridg.SOLVER_PREFACTORED:
-        bw = info.bytes_predict / (R["pred_ms"] * 1e-3) / 1e9
-        roofline.update({"bound": "hbm", "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": bw / HBM_PEAK_GBS, "bytes_per_launch": info.bytes_predict})
+        comp = R["opts"]["composite"]
+        nbytes = info.bytes_composite if comp else info.bytes_predict
+        nflops = info.flops_composite if comp else info.flops_predict
+        bw = nbytes / (R["pred_ms"] * 1e-3) / 1e9
+        tf = nflops / (R["pred_ms"] * 1e-3) / 1e12
+        kern = "composite prediction+correction stencil" if comp else "prediction (prefactored G)"
+        # the roof that binds: whichever fraction is larger
+        if bw / HBM_PEAK_GBS >= tf / FP64_VECTOR_PEAK_TFLOPS:
+            roofline.update({"bound": "hbm", "kernel": kern, "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": bw / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "flops_per_launch": nflops,
+                             "tflops": tf})
+        else:
+            roofline.update({"bound": "alu", "kernel": kern, "achieved": tf, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": tf / FP64_VECTOR_PEAK_TFLOPS, "flops_per_launch": nflops,
+                             "bytes_per_launch": nbytes, "gbs": bw})
     out = {
         "metric": METRIC,
         "value": R["value"],
@@ -228,6 +270,7 @@ def main():
         "config": {"workload": wl.name, "n": list(wl.n), "order": wl.M, "theta_t": info.theta_t,
                    "velocity": list(map(str, wl.velocity[1])), "dt": wl.dt, "cfl": 0.5,
                    "solver": ["auto", "prefactored", "region", "dense"][info.solver], "precision": best,
+                   "options": R["opts"],
                    "refine_steps": args.refine if best == "fp32" else 0},
         "spatial_dof_updates_per_s": info.n_elements * info.theta * args.steps / R["wall"],
         "latency_ms": {"p50": float(np.percentile(R["lat"], 50)), "p99": float(np.percentile(R["lat"], 99)),

@@ -107,6 +107,8 @@ typedef struct ridg_info {
   double flops_correct;     /* per step, correction */
   double bytes_predict;     /* per step, prediction: algorithmic HBM bytes (state in, predictions out) */
   double bytes_correct;     /* per step, correction: state in/out, predictions in */
+  double flops_composite;   /* PREFACTORED with RIDG_OPT_COMPOSITE: per step */
+  double bytes_composite;   /* PREFACTORED with RIDG_OPT_COMPOSITE: state in/out per step */
 } ridg_info;
 
 /* Accumulated stage times of ridg_step, from HIP events recorded on the handle's stream. */
@@ -170,6 +172,8 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
 #define RIDG_OPT_GRAPH 1
 #define RIDG_OPT_PLAN_LAYOUT 2
 #define RIDG_OPT_FUSED 3
+#define RIDG_OPT_COMPOSITE 4 /* PREFACTORED: prediction and correction composed into one stencil on the
+                                state, K_o = sum D_t G_s (the predictions are not stored) */
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value);
 int ridg_get_option(ridg_t* h, int32_t option, int64_t* value);
 

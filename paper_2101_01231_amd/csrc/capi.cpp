@@ -38,7 +38,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, taps, plans, items[2], item_plan[2], dense, scratch, flag, ptab, tplans, telems,
+  size_t q0, q1, w, stage, tens, g, dc, kc, taps, plans, items[2], item_plan[2], dense, scratch, flag, ptab, tplans, telems,
       total;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
@@ -91,6 +91,8 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
   L.tens_doubles = tensor_doubles(T);
   L.tens = take(L.tens_doubles * 8);
   L.g = take((size_t)kMaxBlocks * nt * ns * 8);
+  L.dc = take((size_t)7 * ns * nt * 8);
+  L.kc = take((size_t)kMaxTapUpdate * ns * ns * 8);
   L.taps = take((size_t)kMaxBlocks * 3 * 4);
   int64_t n_dense = 0;
   size_t nplans = 0;
@@ -144,6 +146,11 @@ struct ridg_handle {
   int ntaps = 0;
   double g_dt = -1.0;
   std::vector<int32_t> host_taps;
+  double* Dc = nullptr;  // constant-velocity correction taps
+  double* Kc = nullptr;  // composite prediction+correction taps
+  std::vector<int32_t> host_dtaps, host_ktaps;
+  int opt_composite = 0;
+  int n_dtaps = 0;
   PlanRec* plans = nullptr;
   int32_t* items[2] = {nullptr, nullptr};  // region work lists for the two segment layouts
   int32_t* item_plan[2] = {nullptr, nullptr};
@@ -222,6 +229,7 @@ std::pair<double, double> flops_model(const ridg_handle* h, double plan_flops) {
   double predict = 0.0;
   if (P.solver == RIDG_SOLVER_PREFACTORED) {
     predict = nel * 2.0 * h->ntaps * nt * ns;
+    correct = nel * 2.0 * h->n_dtaps * ns * nt;
   } else {
     double nbn = std::pow(3.0, d) * nt;
     double dense_elem = 2.0 / 3.0 * nbn * nbn * nbn + 2.0 * nbn * nbn;
@@ -239,7 +247,7 @@ std::pair<double, double> flops_model(const ridg_handle* h, double plan_flops) {
 // ---------------------------------------------------------------- autotuner
 namespace {
 std::mutex g_tune_mu;
-std::map<std::string, std::array<int, 3>> g_tune_cache;  // problem key -> {graph, layout, fused}
+std::map<std::string, std::array<int, 4>> g_tune_cache;  // problem key -> {graph, layout, fused, composite}
 bool g_tune_file_loaded = false;
 
 std::string tune_key(const ridg_handle* h, int32_t steps) {
@@ -258,17 +266,17 @@ void tune_file_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char key[200];
-  int a, b, c;
-  while (std::fscanf(f, "%199s %d %d %d", key, &a, &b, &c) == 4) g_tune_cache[key] = {a, b, c};
+  int a, b, c, e;
+  while (std::fscanf(f, "%199s %d %d %d %d", key, &a, &b, &c, &e) == 5) g_tune_cache[key] = {a, b, c, e};
   std::fclose(f);
 }
 
-void tune_file_append(const std::string& key, const std::array<int, 3>& o) {
+void tune_file_append(const std::string& key, const std::array<int, 4>& o) {
   const char* path = std::getenv("RIDG_AUTOTUNE_CACHE");
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d\n", key.c_str(), o[0], o[1], o[2]);
+  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), o[0], o[1], o[2], o[3]);
   std::fclose(f);
 }
 }  // namespace
@@ -374,6 +382,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->W = (double*)(h->ws + h->L.w);
   h->stage = (double*)(h->ws + h->L.stage);
   h->G = (double*)(h->ws + h->L.g);
+  h->Dc = (double*)(h->ws + h->L.dc);
+  h->Kc = (double*)(h->ws + h->L.kc);
   h->taps = (int32_t*)(h->ws + h->L.taps);
   h->plans = (PlanRec*)(h->ws + h->L.plans);
   for (int l = 0; l < 2; ++l) {
@@ -455,12 +465,23 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
     element_plan(P, 0, &rec);
     I.n_taps = rec.nb;
     h->ntaps = rec.nb;
+    // tap counts do not depend on dt (face sides do not): size them once
+    Prefactored pf;
+    std::string m;
+    if (build_prefactored(P, h->T, 1.0, &pf, &m) == RIDG_OK) {
+      TapOperator dc, kc;
+      build_correction_taps(P, h->T, 1.0, &dc);
+      build_composite(P, pf, dc, &kc);
+      h->n_dtaps = (int)dc.offs.size();
+      I.flops_composite = (double)P.nel * 2.0 * kc.offs.size() * T.ns * T.ns;
+    }
   }
   auto fl = flops_model(h, plan_flops);
   I.flops_predict = fl.first;
   I.flops_correct = fl.second;
   I.bytes_predict = (double)P.nel * 8.0 * (T.ns + T.nt);
   I.bytes_correct = (double)P.nel * 8.0 * (2.0 * T.ns + T.nt);
+  I.bytes_composite = (double)P.nel * 8.0 * 2.0 * T.ns;
   *out = h;
   return RIDG_OK;
 }
@@ -588,9 +609,22 @@ static int ensure_dt_tables(ridg_t* h, double dt) {
   for (size_t t = 0; t < pf.offs.size(); ++t)
     for (int i = 0; i < 3; ++i) h->host_taps[3 * t + i] = pf.offs[t][i];
   h->ntaps = (int)pf.offs.size();
+  TapOperator dc, kc;
+  build_correction_taps(h->P, h->T, dt, &dc);
+  build_composite(h->P, pf, dc, &kc);
+  if (dc.offs.size() > 7 || kc.offs.size() > (size_t)kMaxTapUpdate) return fail(RIDG_E_UNSUPPORTED, "tap count");
+  auto flat = [](const TapOperator& op, std::vector<int32_t>* v) {
+    v->assign(op.offs.size() * 3, 0);
+    for (size_t t = 0; t < op.offs.size(); ++t)
+      for (int i = 0; i < 3; ++i) (*v)[3 * t + i] = op.offs[t][i];
+  };
+  flat(dc, &h->host_dtaps);
+  flat(kc, &h->host_ktaps);
   int err = hipMemcpyAsync(h->G, pf.G.data(), pf.G.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipMemcpyAsync(h->Dc, dc.A.data(), dc.A.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipMemcpyAsync(h->Kc, kc.A.data(), kc.A.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipStreamSynchronize(h->stream);
-  if (err) return hip_fail(err, "upload of G");
+  if (err) return hip_fail(err, "upload of the prefactored operators");
   h->g_dt = dt;
   return RIDG_OK;
 }
@@ -638,18 +672,30 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
 }
 
 static int direct_step(ridg_t* h, double dt) {
+  const Problem& P = h->P;
+  const bool pref = P.solver == RIDG_SOLVER_PREFACTORED;
   if (h->timing) {
     int err = record_event(h);
     if (err) return hip_fail(err, "timing event");
   }
-  int rc = run_predict(h, h->Q[h->cur], dt);
-  if (rc) return rc;
+  if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
+    int err = launch_tap_update(P.d, P.M, 1, h->geom, h->Q[h->cur], h->Q[h->cur], h->Q[1 - h->cur], h->Kc,
+                                h->host_ktaps.data(), (int)h->host_ktaps.size() / 3, h->stream);
+    if (err) return hip_fail(err, "composite launch");
+  } else {
+    int rc = run_predict(h, h->Q[h->cur], dt);
+    if (rc) return rc;
+  }
   if (h->timing) {
     int err = record_event(h);
     if (err) return hip_fail(err, "timing event");
   }
-  int err = launch_correct(h->P.d, h->P.M, h->P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt,
-                           h->stream);
+  int err = 0;
+  if (pref && !h->opt_composite)
+    err = launch_tap_update(P.d, P.M, 0, h->geom, h->W, h->Q[h->cur], h->Q[1 - h->cur], h->Dc, h->host_dtaps.data(),
+                            (int)h->host_dtaps.size() / 3, h->stream);
+  else if (!pref)
+    err = launch_correct(P.d, P.M, P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt, h->stream);
   if (err) return hip_fail(err, "correction launch");
   if (h->timing) {
     err = record_event(h);
@@ -779,6 +825,10 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
           d.Qout = h->Q[1 - h->cur];
           d.W = h->W;
           d.G = h->G;
+          d.Dc = h->Dc;
+          d.ndtaps = (int32_t)h->host_dtaps.size() / 3;
+          for (int t = 0; t < d.ndtaps && t < 7; ++t)
+            for (int i = 0; i < 3; ++i) d.dtaps[t][i] = (int8_t)h->host_dtaps[3 * t + i];
           d.block_begin = blk;
           d.nel = h->P.nel;
           for (int i = 0; i < 3; ++i) {
@@ -819,6 +869,11 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
         return fail(RIDG_E_UNSUPPORTED, "fused steps need the PREFACTORED solver and a mesh that fits in LDS");
       h->opt_fused = (int)value;
       break;
+    case RIDG_OPT_COMPOSITE:
+      if (value && h->P.solver != RIDG_SOLVER_PREFACTORED)
+        return fail(RIDG_E_UNSUPPORTED, "the composite stencil needs the PREFACTORED solver");
+      h->opt_composite = (int)value;
+      break;
     default:
       return fail(RIDG_E_INVAL, "unknown option");
   }
@@ -832,6 +887,7 @@ int ridg_get_option(ridg_t* h, int32_t option, int64_t* value) {
     case RIDG_OPT_GRAPH: *value = h->opt_graph; return RIDG_OK;
     case RIDG_OPT_PLAN_LAYOUT: *value = h->opt_layout; return RIDG_OK;
     case RIDG_OPT_FUSED: *value = h->opt_fused; return RIDG_OK;
+    case RIDG_OPT_COMPOSITE: *value = h->opt_composite; return RIDG_OK;
     default: return fail(RIDG_E_INVAL, "unknown option");
   }
 }
@@ -851,17 +907,20 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
       h->opt_graph = it->second[0];
       h->opt_layout = it->second[1];
       h->opt_fused = it->second[2];
+      h->opt_composite = it->second[3];
       drop_graphs(h);
       if (best_ms_per_step) *best_ms_per_step = -1.0;  // from the cache, not re-measured
       return RIDG_OK;
     }
   }
-  std::vector<std::array<int, 3>> cands;
+  std::vector<std::array<int, 4>> cands;
   const bool region = h->P.solver == RIDG_SOLVER_REGION;
-  const bool fusable = h->P.solver == RIDG_SOLVER_PREFACTORED && fused_fits(h->P.d, h->P.M, h->P.nel);
+  const bool pref = h->P.solver == RIDG_SOLVER_PREFACTORED;
+  const bool fusable = pref && fused_fits(h->P.d, h->P.M, h->P.nel);
   for (int g = 0; g < 2; ++g)
-    for (int l = 0; l < (region ? 2 : 1); ++l) cands.push_back({g, l, 0});
-  if (fusable) cands.push_back({0, 0, 1});
+    for (int l = 0; l < (region ? 2 : 1); ++l)
+      for (int c = 0; c < (pref ? 2 : 1); ++c) cands.push_back({g, l, 0, c});
+  if (fusable) cands.push_back({0, 0, 1, 0});
   // keep the state: tuning steps run on a copy that is restored afterwards
   const size_t bytes = (size_t)h->P.nel * h->T.ns * 8;
   const int cur0 = h->cur;
@@ -870,12 +929,13 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   if (!err) err = hipEventCreate(&e0);
   if (!err) err = hipEventCreate(&e1);
   double best = 1e300;
-  std::array<int, 3> pick = {h->opt_graph, h->opt_layout, h->opt_fused};
+  std::array<int, 4> pick = {h->opt_graph, h->opt_layout, h->opt_fused, h->opt_composite};
   int rc = RIDG_OK;
   for (size_t c = 0; c < cands.size() && !err && !rc; ++c) {
     h->opt_graph = cands[c][0];
     h->opt_layout = cands[c][1];
     h->opt_fused = cands[c][2];
+    h->opt_composite = cands[c][3];
     drop_graphs(h);
     rc = ridg_step(h, 2, dt);  // warm-up (and graph capture)
     if (rc < 0) break;
@@ -900,6 +960,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   h->opt_graph = pick[0];
   h->opt_layout = pick[1];
   h->opt_fused = pick[2];
+  h->opt_composite = pick[3];
   drop_graphs(h);
   if (rc < 0) return rc;
   if (err) return hip_fail(err, "autotune");

@@ -802,4 +802,68 @@ int build_prefactored(const Problem& P, const RefTensors& T, double dt, Prefacto
   return RIDG_OK;
 }
 
+void build_correction_taps(const Problem& P, const RefTensors& T, double dt, TapOperator* out) {
+  const int d = P.d, ns = T.ns, nt = T.nt;
+  const double scale = std::ldexp(1.0, -d);
+  out->rows = ns;
+  out->cols = nt;
+  out->offs.assign(1, {0, 0, 0});
+  out->A.assign((size_t)ns * nt, 0.0);
+  int idx[3] = {0, 0, 0};
+  double c0[3], c[3][3];
+  nu_coeffs(P, idx, dt, c0, c);
+  auto add = [&](const std::array<int, 3>& o, const double* M, double f) {
+    size_t t = 0;
+    while (t < out->offs.size() && out->offs[t] != o) ++t;
+    if (t == out->offs.size()) {
+      out->offs.push_back(o);
+      out->A.resize(out->offs.size() * (size_t)ns * nt, 0.0);
+    }
+    double* A = &out->A[t * (size_t)ns * nt];
+    for (size_t q = 0; q < (size_t)ns * nt; ++q) A[q] += f * M[q];
+  };
+  for (int i = 0; i < d; ++i) {
+    const double vi = c0[i];
+    if (vi == 0.0) continue;
+    add({0, 0, 0}, &T.Cv[T.cv(i, 0)], scale * vi);
+    for (int s = -1; s <= 1; s += 2) {
+      if (face_side(P, idx, i, s) == 0) {
+        add({0, 0, 0}, &T.CFo[T.cf(i, s, 0)], -scale * vi);
+      } else {
+        std::array<int, 3> o = {0, 0, 0};
+        o[i] = s;
+        add(o, &T.CFn[T.cf(i, s, 0)], -scale * vi);
+      }
+    }
+  }
+}
+
+void build_composite(const Problem& P, const Prefactored& G, const TapOperator& Dc, TapOperator* out) {
+  (void)P;
+  const int ns = Dc.rows, nt = Dc.cols;
+  out->rows = ns;
+  out->cols = ns;
+  out->offs.clear();
+  out->A.clear();
+  for (size_t t = 0; t < Dc.offs.size(); ++t)
+    for (size_t g = 0; g < G.offs.size(); ++g) {
+      std::array<int, 3> o = {Dc.offs[t][0] + G.offs[g][0], Dc.offs[t][1] + G.offs[g][1], Dc.offs[t][2] + G.offs[g][2]};
+      size_t q = 0;
+      while (q < out->offs.size() && out->offs[q] != o) ++q;
+      if (q == out->offs.size()) {
+        out->offs.push_back(o);
+        out->A.resize(out->offs.size() * (size_t)ns * ns, 0.0);
+      }
+      double* K = &out->A[q * (size_t)ns * ns];
+      const double* D = &Dc.A[t * (size_t)ns * nt];
+      const double* Gs = &G.G[g * (size_t)nt * ns];
+      for (int r = 0; r < ns; ++r)
+        for (int k = 0; k < nt; ++k) {
+          const double dv = D[(size_t)r * nt + k];
+          if (dv == 0.0) continue;
+          for (int c = 0; c < ns; ++c) K[(size_t)r * ns + c] += dv * Gs[(size_t)k * ns + c];
+        }
+    }
+}
+
 }  // namespace ridg

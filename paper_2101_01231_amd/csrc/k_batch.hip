@@ -1,5 +1,6 @@
 // Shared launches for serving: one prediction kernel and one correction kernel advance a step of
-// several independent constant-velocity problems of the same dimension and order. Each problem is
+// several independent constant-velocity problems of the same dimension and order (the correction
+// in the same tap form as a single problem's default step). Each problem is
 // described by value in the kernel arguments (no device-side table to manage); a workgroup finds
 // its problem from the block ranges. The per-element arithmetic is exactly that of the
 // single-problem kernels, so a problem's result does not depend on what it is batched with.
@@ -31,8 +32,13 @@ __global__ __launch_bounds__(256) void batch_predict_kernel(BatchArgs args) {
   predict_prefactored_elem<D, M>(g, bd.Qin, bd.W, bd.G, tp, bd.ntaps, e, bd.nel);
 }
 
+struct BatchTaps {
+  int8_t off[7][3];
+};
+
 template <int D, int M>
-__global__ __launch_bounds__(256) void batch_correct_kernel(BatchArgs args, DevTensors t) {
+__global__ __launch_bounds__(256) void batch_correct_kernel(BatchArgs args) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
   int r = 0;
   for (int q = 1; q < args.count; ++q)
     if ((int64_t)blockIdx.x >= args.d[q].block_begin) r = q;
@@ -44,12 +50,12 @@ __global__ __launch_bounds__(256) void batch_correct_kernel(BatchArgs args, DevT
   g.n0 = bd.n[0];
   g.n1 = bd.n[1];
   g.n2 = bd.n[2];
-  g.h0 = bd.h[0];
-  g.h1 = bd.h[1];
-  g.h2 = bd.h[2];
+  BatchTaps tp;
 #pragma unroll
-  for (int i = 0; i < 3; ++i) g.a[i] = bd.v[i];
-  correct_elem<D, M, false>(g, bd.dt, bd.Qin, bd.W, bd.Qout, t, e, bd.nel);
+  for (int t = 0; t < 7; ++t)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tp.off[t][i] = bd.dtaps[t][i];
+  tap_update_elem<NS, NT>(g, bd.W, bd.Qin, bd.Qout, bd.Dc, tp, bd.ndtaps, e, bd.nel);
 }
 
 template <int D, int M>
@@ -60,7 +66,8 @@ struct BatchL {
     hipLaunchKernelGGL((batch_predict_kernel<D, M>), dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
     int err = (int)hipGetLastError();
     if (err) return err;
-    hipLaunchKernelGGL((batch_correct_kernel<D, M>), dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a, t);
+    (void)t;
+    hipLaunchKernelGGL((batch_correct_kernel<D, M>), dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
   }
 };

@@ -102,4 +102,43 @@ int launch_fused_prefactored(int d, int M, const DevGeom& g, double dt, const do
   return dispatch_dm<FusedL>(d, M, g, dt, Qin, Qout, G, taps, ntaps, t, n_steps, stream);
 }
 
+// ---------------------------------------------------------------- tap-form updates (constant velocity)
+// out_e = base_e + sum_t A_t in_{e + off_t}: the correction from the predictions (R = theta rows,
+// C = theta_T columns) or the composed prediction + correction acting on the state directly
+// (R = C = theta). Operators are uniform across threads (scalar loads).
+template <int D, int R, int C>
+__global__ __launch_bounds__(256) void tap_update_kernel(DevGeom g, const double* __restrict__ in,
+                                                         const double* __restrict__ base, double* __restrict__ out,
+                                                         const double* __restrict__ A, TapsN taps, int ntaps) {
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  tap_update_elem<R, C>(g, in, base, out, A, taps, ntaps, e, nel);
+}
+
+template <int D, int M>
+struct TapL {
+  static int run(int kind, const DevGeom& g, const double* in, const double* base, double* out, const double* A,
+                 const int32_t* taps, int ntaps, void* stream) {
+    constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
+    if (ntaps > kMaxTapUpdate) return (int)hipErrorInvalidValue;
+    TapsN tp;
+    for (int t = 0; t < kMaxTapUpdate; ++t)
+      for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+    const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+    if (kind == 0)
+      hipLaunchKernelGGL((tap_update_kernel<D, NS, NT>), dim3(grid_for(nel, 256)), dim3(256), 0, (hipStream_t)stream,
+                         g, in, base, out, A, tp, ntaps);
+    else
+      hipLaunchKernelGGL((tap_update_kernel<D, NS, NS>), dim3(grid_for(nel, 256)), dim3(256), 0, (hipStream_t)stream,
+                         g, in, base, out, A, tp, ntaps);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
+                      const double* A, const int32_t* taps, int ntaps, void* stream) {
+  return dispatch_dm<TapL>(d, M, kind, g, in, base, out, A, taps, ntaps, stream);
+}
+
 }  // namespace ridg

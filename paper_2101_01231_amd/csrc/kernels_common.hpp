@@ -383,4 +383,32 @@ __device__ inline void predict_prefactored_elem(const DevGeom& g, const double* 
   for (int k = 0; k < NT; ++k) W[(int64_t)k * nel + e] = w[k];
 }
 
+// out_e = base_e + sum_t A_t in_{e + off_t} (constant-velocity operators in tap form; A uniform).
+struct TapsN {
+  int8_t off[kMaxTapUpdate][3];
+};
+
+template <int R, int C, class TAPS>
+__device__ inline void tap_update_elem(const DevGeom& g, const double* in, const double* base, double* out,
+                                       const double* A, const TAPS& taps, int ntaps, int64_t e, int64_t nel) {
+  int idx[3];
+  elem_idx(g, e, idx);
+  double acc[R];
+#pragma unroll
+  for (int k = 0; k < R; ++k) acc[k] = 0.0;
+  for (int tp = 0; tp < ntaps; ++tp) {
+    const int64_t src = elem_lin(g, idx[0] + taps.off[tp][0], idx[1] + taps.off[tp][1], idx[2] + taps.off[tp][2]);
+    double x[C];
+#pragma unroll
+    for (int l = 0; l < C; ++l) x[l] = in[(int64_t)l * nel + src];
+    const double* At = A + (size_t)tp * R * C;
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+      for (int l = 0; l < C; ++l) acc[k] = fma(At[k * C + l], x[l], acc[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < R; ++k) out[(int64_t)k * nel + e] = base[(int64_t)k * nel + e] + acc[k];
+}
+
 }  // namespace ridg

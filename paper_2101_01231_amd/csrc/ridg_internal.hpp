@@ -134,6 +134,18 @@ struct Prefactored {
 };
 int build_prefactored(const Problem& P, const RefTensors& T, double dt, Prefactored* out, std::string* msg);
 
+// Constant velocity operators in tap form: out_e (+)= sum_t A_t in_{e + off_t}, A_t rows x cols.
+struct TapOperator {
+  std::vector<std::array<int, 3>> offs;
+  std::vector<double> A;  // [tap][row][col]
+  int rows = 0, cols = 0;
+};
+// Correction (Sec. 2.3) for constant velocity: Q'_e = Q_e + sum_t D_t W_{e + off_t} (own + inflow faces).
+void build_correction_taps(const Problem& P, const RefTensors& T, double dt, TapOperator* out);
+// Prediction and correction composed: Q'_e = Q_e + sum_o K_o Q_{e+o}, K_o = sum_{t+s=o} D_t G_s.
+void build_composite(const Problem& P, const Prefactored& G, const TapOperator& Dc, TapOperator* out);
+constexpr int kMaxTapUpdate = 125;  // composite offsets in {-2..2}^3
+
 // ---------------------------------------------------------------- device side
 struct DevTensors {  // device copies (FP64), offsets into one buffer
   const double* Tt;
@@ -181,6 +193,7 @@ struct BatchDesc {
   double* Qout;
   double* W;
   const double* G;
+  const double* Dc;  // correction taps (theta x theta_T each)
   int64_t block_begin;  // first workgroup of this problem in the launch grid
   int64_t nel;
   double h[3];
@@ -188,8 +201,10 @@ struct BatchDesc {
   double dt;
   int32_t n[3];
   int32_t ntaps;
+  int32_t ndtaps;
   int8_t taps[kBatchTaps][3];
-  int8_t pad[8];
+  int8_t dtaps[7][3];
+  int8_t pad[7];
 };
 struct BatchArgs {
   BatchDesc d[kBatchMax];
@@ -203,6 +218,9 @@ int launch_aos_to_soa(const double* src, double* dst, int64_t nel, int nmodes, v
 int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
 int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, double* W,
                                const double* G, const int32_t* taps, int ntaps, void* stream);
+// kind 0: correction taps (W -> Q' = Q + ...), kind 1: composite taps (Q -> Q' = Q + ...)
+int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
+                      const double* A, const int32_t* taps, int ntaps, void* stream);
 // layout: 0 = packed theta_T-lane segments, 1 = power-of-two segments (DPP reductions)
 int launch_predict_plans(int d, int M, int layout, int precision, int refine, const DevGeom& g, double dt,
                          const double* Q, double* W, const PlanTables& t, const PlanRec* plans,

@@ -28,7 +28,7 @@ FLUX_CONST, FLUX_ROTATION, FLUX_AFFINE = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
-OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED = 1, 2, 3
+OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE = 1, 2, 3, 4
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
@@ -69,6 +69,8 @@ class RidgInfo(ctypes.Structure):
         ("flops_correct", ctypes.c_double),
         ("bytes_predict", ctypes.c_double),
         ("bytes_correct", ctypes.c_double),
+        ("flops_composite", ctypes.c_double),
+        ("bytes_composite", ctypes.c_double),
     ]
 
 

@@ -58,7 +58,8 @@ def test_fused_small_mesh_matches_direct(d, n, M, v):
     dt = 0.45 / max(n) / max(abs(x) for x in v)
     direct = _run(p, q0, dt, 25)
     fused = _run(p, q0, dt, 25, options=[(ridg.OPT_FUSED, 1)], chunks=[10, 15])
-    assert np.array_equal(direct, fused)
+    # the fused kernel applies the correction term by term, the default step in precombined tap form
+    assert np.linalg.norm(fused - direct) / np.linalg.norm(direct) <= 1e-13
 
 
 def test_fused_rejected_when_not_applicable():
@@ -88,4 +89,18 @@ def test_autotune_keeps_state_and_results(kind):
     sim.step(7, dt)
     got = sim.get_state()
     sim.close()
-    assert np.array_equal(got, ref)
+    # the tuner may pick a composed or fused variant: same scheme, different rounding order
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-13
+
+
+@pytest.mark.parametrize("d,n,M,v", [(3, (6, 5, 4), 3, (1.0, 1.0, 1.0)), (2, (24, 20), 4, (1.0, 0.5)),
+                                     (1, (40,), 5, (-0.8,)), (2, (9, 8), 2, (0.0, -0.6))])
+def test_composite_and_tap_correction_match_oracle(d, n, M, v):
+    """Constant velocity: the tap-form correction (default) and the composite stencil against the oracle."""
+    p = ridg.make_problem(d, n, M, velocity=v)
+    q0 = I.random_state(d, n, M, seed=8)
+    dt = 0.45 * min(1.0 / k for k in n) / max(abs(x) for x in v)
+    ref = S.step(S.Problem(d=d, n=n, M=M, velocity=("const", v)), q0, dt, 3)
+    for opts in ([], [(ridg.OPT_COMPOSITE, 1)]):
+        got = _run(p, q0, dt, 3, options=opts)
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12, opts
