@@ -162,11 +162,12 @@ int ridg_enable_timing(ridg_t* h, int32_t on);
 /* Synchronise the stream and return (and reset) the accumulated stage times. */
 int ridg_get_timing(ridg_t* h, ridg_timing* out);
 
-/* Execution options (all default 0). Values are 0 or 1.
+/* Execution options (all default 0). Values are 0 or 1 unless stated.
  *   RIDG_OPT_GRAPH: replay a captured HIP graph of two steps instead of launching kernels one by
  *     one (recaptured when dt or an option changes; not used while stage timing is on).
  *   RIDG_OPT_PLAN_LAYOUT (REGION): 0 = theta_T-lane segments packed in the wavefront, 1 = segments
- *     padded to a power of two (DPP reductions).
+ *     padded to a power of two (DPP reductions), 2 = two regions per packed segment with their
+ *     eliminations interleaved (RIDG_FP64 only). Every layout gives bitwise the same results.
  *   RIDG_OPT_FUSED (PREFACTORED, meshes whose state and predictions fit in 160 KB of LDS): run all
  *     n_steps of a ridg_step call in one single-workgroup kernel. */
 #define RIDG_OPT_GRAPH 1

@@ -38,11 +38,11 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, dc, kc, taps, plans, items[2], item_plan[2], dense, scratch, flag, ptab, tplans, telems,
+  size_t q0, q1, w, stage, tens, g, dc, kc, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
       total;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
-  int64_t n_items[2] = {0, 0}, n_dense = 0, scratch_elems = 0;
+  int64_t n_items[kLayouts] = {0, 0, 0}, n_dense = 0, scratch_elems = 0;
   size_t tens_doubles = 0;
 };
 
@@ -75,7 +75,7 @@ void build_items(const RegionPlans& R, int ipw, std::vector<int32_t>* items, std
   }
 }
 
-Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, const int64_t n_items[2]) {
+Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, const int64_t n_items[kLayouts]) {
   Layout L;
   const size_t nel = (size_t)P.nel, ns = T.ns, nt = T.nt;
   size_t off = 0;
@@ -103,7 +103,7 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
     n_dense = P.nel;
   }
   L.plans = take(std::max<size_t>(nplans, 1) * sizeof(PlanRec));
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < kLayouts; ++l) {
     L.n_items[l] = n_items[l];
     L.items[l] = take(std::max<int64_t>(n_items[l], 1) * 4);
     L.item_plan[l] = take(std::max<int64_t>(n_items[l], 1) * 4);
@@ -152,8 +152,8 @@ struct ridg_handle {
   int opt_composite = 0;
   int n_dtaps = 0;
   PlanRec* plans = nullptr;
-  int32_t* items[2] = {nullptr, nullptr};  // region work lists for the two segment layouts
-  int32_t* item_plan[2] = {nullptr, nullptr};
+  int32_t* items[kLayouts] = {};  // region work lists, one per segment layout
+  int32_t* item_plan[kLayouts] = {};
   // options (ridg_set_option)
   int opt_graph = 0, opt_layout = 0, opt_fused = 0;
   hipGraphExec_t graph[2] = {nullptr, nullptr};  // two captured steps, per state-buffer parity
@@ -307,11 +307,11 @@ int ridg_workspace_bytes(const ridg_problem* problem, size_t* bytes) {
   if (rc) return fail(rc, msg);
   Basis B = make_basis(P.d, P.M);
   RefTensors T = make_tensors(B);
-  int64_t n_items[2] = {0, 0};
+  int64_t n_items[kLayouts] = {0, 0, 0};
   RegionPlans R;
   if (P.solver == RIDG_SOLVER_REGION) {
     R = build_plans(P);
-    for (int l = 0; l < 2; ++l) {
+    for (int l = 0; l < kLayouts; ++l) {
       std::vector<int32_t> it, ip;
       build_items(R, items_per_wave(P.d, P.M, l), &it, &ip);
       n_items[l] = (int64_t)it.size();
@@ -335,11 +335,11 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->B = make_basis(P.d, P.M);
   h->T = make_tensors(h->B);
   RegionPlans R;
-  std::vector<int32_t> items[2], item_plan[2];
+  std::vector<int32_t> items[kLayouts], item_plan[kLayouts];
   double plan_flops = 0.0;
   if (P.solver == RIDG_SOLVER_REGION) {
     R = build_plans(P);
-    for (int l = 0; l < 2; ++l) build_items(R, items_per_wave(P.d, P.M, l), &items[l], &item_plan[l]);
+    for (int l = 0; l < kLayouts; ++l) build_items(R, items_per_wave(P.d, P.M, l), &items[l], &item_plan[l]);
     // flop tally of the plan work actually run (per element, padding excluded)
     const double nt = h->T.nt, ns = h->T.ns;
     const double np_active = (P.flux == RIDG_FLUX_CONST) ? 1.0 : (double)P.d;
@@ -369,7 +369,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
       plan_flops += 2.0 * nt * nt;  // W_centre = alpha + B x
     }
   }
-  const int64_t n_items[2] = {(int64_t)items[0].size(), (int64_t)items[1].size()};
+  const int64_t n_items[kLayouts] = {(int64_t)items[0].size(), (int64_t)items[1].size(), (int64_t)items[2].size()};
   h->L = make_layout(P, h->T, &R, n_items);
   if (ws_bytes < h->L.total) {
     delete h;
@@ -386,7 +386,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->Kc = (double*)(h->ws + h->L.kc);
   h->taps = (int32_t*)(h->ws + h->L.taps);
   h->plans = (PlanRec*)(h->ws + h->L.plans);
-  for (int l = 0; l < 2; ++l) {
+  for (int l = 0; l < kLayouts; ++l) {
     h->items[l] = (int32_t*)(h->ws + h->L.items[l]);
     h->item_plan[l] = (int32_t*)(h->ws + h->L.item_plan[l]);
   }
@@ -418,7 +418,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   if (!err && P.solver == RIDG_SOLVER_REGION) {
     if (!R.plans.empty())
       err = hipMemcpyAsync(h->plans, R.plans.data(), R.plans.size() * sizeof(PlanRec), hipMemcpyHostToDevice, h->stream);
-    for (int l = 0; l < 2 && !err; ++l) {
+    for (int l = 0; l < kLayouts && !err; ++l) {
       if (!items[l].empty())
         err = hipMemcpyAsync(h->items[l], items[l].data(), items[l].size() * 4, hipMemcpyHostToDevice, h->stream);
       if (!err && !item_plan[l].empty())
@@ -853,7 +853,8 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
 
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
-  if (value != 0 && value != 1) return fail(RIDG_E_INVAL, "option values are 0 or 1");
+  const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : 1;
+  if (value < 0 || value > vmax) return fail(RIDG_E_INVAL, "option value out of range");
   int err = hipStreamSynchronize(h->stream);
   if (err) return hip_fail(err, "hipStreamSynchronize");
   switch (option) {
@@ -862,6 +863,8 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
       break;
     case RIDG_OPT_PLAN_LAYOUT:
       if (h->P.solver != RIDG_SOLVER_REGION && value) return fail(RIDG_E_UNSUPPORTED, "plan layout applies to REGION");
+      if (value == 2 && h->P.precision != RIDG_FP64)
+        return fail(RIDG_E_UNSUPPORTED, "the two-region layout is FP64 only");
       h->opt_layout = (int)value;
       break;
     case RIDG_OPT_FUSED:
@@ -918,7 +921,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   const bool pref = h->P.solver == RIDG_SOLVER_PREFACTORED;
   const bool fusable = pref && fused_fits(h->P.d, h->P.M, h->P.nel);
   for (int g = 0; g < 2; ++g)
-    for (int l = 0; l < (region ? 2 : 1); ++l)
+    for (int l = 0; l < (region ? (h->P.precision == RIDG_FP64 ? 3 : 2) : 1); ++l)
       for (int c = 0; c < (pref ? 2 : 1); ++c) cands.push_back({g, l, 0, c});
   if (fusable) cands.push_back({0, 0, 1, 0});
   // keep the state: tuning steps run on a copy that is restored afterwards

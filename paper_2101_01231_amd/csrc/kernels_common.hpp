@@ -200,6 +200,77 @@ __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle,
   wave_sync();
 }
 
+// Two independent systems per segment (row k of each in lane k): the pivot searches, publishes
+// and updates of the two eliminations are interleaved so that the latency of one hides behind
+// the other's work; one wave-level sync per column serves both.
+template <int NT, int LB, bool POW2, int SEGW>
+__device__ inline void seg_solve2(double (&a)[2][NT], double (&rhs)[2], int k, bool idle,
+                                  const int (&addr)[LB > 0 ? LB : 1], double* piv, double* x0, double* x1) {
+  constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + 2;
+  bool used0 = idle, used1 = idle;
+  int step0 = -1, step1 = -1;
+  double inv0 = 0.0, inv1 = 0.0;
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    double* pv0 = piv + ((c & 1) * 2 + 0) * PS;
+    double* pv1 = piv + ((c & 1) * 2 + 1) * PS;
+    unsigned k0 = 0u, k1 = 0u;
+    if (!used0) k0 = (__float_as_uint((float)fabs(a[0][c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if (!used1) k1 = (__float_as_uint((float)fabs(a[1][c])) & ~LMASK) | (LMASK - (unsigned)k);
+    if constexpr (POW2) {
+      k0 = seg_max_pow2<SEGW>(k0);
+      k1 = seg_max_pow2<SEGW>(k1);
+    } else {
+#pragma unroll
+      for (int r = 0; r < LB; ++r) {
+        const unsigned o0 = (unsigned)__builtin_amdgcn_ds_bpermute(addr[r], (int)k0);
+        const unsigned o1 = (unsigned)__builtin_amdgcn_ds_bpermute(addr[r], (int)k1);
+        k0 = max(k0, o0);
+        k1 = max(k1, o1);
+      }
+    }
+    const bool p0 = (k == (int)(LMASK - (k0 & LMASK))) && !idle;
+    const bool p1 = (k == (int)(LMASK - (k1 & LMASK))) && !idle;
+    if (p0) {
+      inv0 = recip(a[0][c]);
+      volatile __attribute__((address_space(3))) double* vp = (volatile __attribute__((address_space(3))) double*)pv0;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) vp[j] = a[0][j];
+      vp[NT] = rhs[0];
+      vp[NT + 1] = inv0;
+      used0 = true;
+      step0 = c;
+    }
+    if (p1) {
+      inv1 = recip(a[1][c]);
+      volatile __attribute__((address_space(3))) double* vp = (volatile __attribute__((address_space(3))) double*)pv1;
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) vp[j] = a[1][j];
+      vp[NT] = rhs[1];
+      vp[NT + 1] = inv1;
+      used1 = true;
+      step1 = c;
+    }
+    wave_sync();
+    if (!p0 && !idle) {
+      const double l = a[0][c] * pv0[NT + 1];
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[0][j] = fma(-l, pv0[j], a[0][j]);
+      rhs[0] = fma(-l, pv0[NT], rhs[0]);
+    }
+    if (!p1 && !idle) {
+      const double l = a[1][c] * pv1[NT + 1];
+#pragma unroll
+      for (int j = c + 1; j < NT; ++j) a[1][j] = fma(-l, pv1[j], a[1][j]);
+      rhs[1] = fma(-l, pv1[NT], rhs[1]);
+    }
+  }
+  if (step0 >= 0) x0[step0] = rhs[0] * inv0;
+  if (step1 >= 0) x1[step1] = rhs[1] * inv1;
+  wave_sync();
+}
+
 // Reduced-precision variant: Gauss-Jordan with partial pivoting in FP32 on the FP32 image of the
 // FP64-assembled block, then `refine` sweeps of iterative refinement: the residual r = b - A x is
 // formed in FP64 from the FP64 row, and the correction is obtained by replaying the FP32

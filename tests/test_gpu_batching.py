@@ -42,13 +42,39 @@ def test_graph_replay_matches_direct(problem_kind):
     assert np.array_equal(direct, graph)
 
 
-def test_plan_layouts_agree():
-    p, q0, dt = _rot(24, 4), I.random_state(2, (24, 24), 4, seed=4), 1.0 / 24
+@pytest.mark.parametrize("case", ["rotation", "const3d", "const1d"])
+def test_plan_layouts_agree(case):
+    """Every segment layout of the region-solve kernel gives bitwise the same steps (same arithmetic)."""
+    if case == "rotation":
+        p, q0, dt = _rot(24, 4), I.random_state(2, (24, 24), 4, seed=4), 1.0 / 24
+        ref_prob = S.Problem(d=2, n=(24, 24), M=4, velocity=("rotation", (0.5, 0.5)))
+    elif case == "const3d":
+        v = (1.0, -0.5, 0.25)
+        p = ridg.make_problem(3, (5, 6, 7), 3, velocity=v, solver=ridg.SOLVER_REGION)
+        q0, dt = I.random_state(3, (5, 6, 7), 3, seed=9), 0.05
+        ref_prob = S.Problem(d=3, n=(5, 6, 7), M=3, velocity=("const", v))
+    else:
+        p = ridg.make_problem(1, (29,), 5, velocity=(-0.7,), solver=ridg.SOLVER_REGION)
+        q0, dt = I.random_state(1, (29,), 5, seed=10), 0.4 / 29 / 0.7
+        ref_prob = S.Problem(d=1, n=(29,), M=5, velocity=("const", (-0.7,)))
+    print(f"[gpu] plan layouts {case}", flush=True)
     a = _run(p, q0, dt, 3)
-    b = _run(p, q0, dt, 3, options=[(ridg.OPT_PLAN_LAYOUT, 1)])
-    assert np.array_equal(a, b)
-    ref = S.step(S.Problem(d=2, n=(24, 24), M=4, velocity=("rotation", (0.5, 0.5))), q0, dt, 3)
-    assert np.linalg.norm(b - ref) / np.linalg.norm(ref) <= 1e-12
+    for lay in (1, 2):
+        b = _run(p, q0, dt, 3, options=[(ridg.OPT_PLAN_LAYOUT, lay)])
+        assert np.array_equal(a, b), lay
+    ref = S.step(ref_prob, q0, dt, 3)
+    assert np.linalg.norm(a - ref) / np.linalg.norm(ref) <= 1e-12
+
+
+def test_two_region_layout_rejected_for_fp32():
+    p = ridg.make_problem(2, (16, 16), 3, flux=ridg.FLUX_ROTATION, rot_center=(0.5, 0.5),
+                          precision=ridg.FP32_REFINE, refine_steps=2)
+    sim = ridg.Simulation(p)
+    with pytest.raises(ridg.RidgError):
+        sim.set_option(ridg.OPT_PLAN_LAYOUT, 2)
+    with pytest.raises(ridg.RidgError):
+        sim.set_option(ridg.OPT_PLAN_LAYOUT, 3)
+    sim.close()
 
 
 @pytest.mark.parametrize("d,n,M,v", [(1, (64,), 3, (1.0,)), (1, (37,), 5, (-0.6,)), (2, (12, 10), 3, (0.8, -0.4))])
