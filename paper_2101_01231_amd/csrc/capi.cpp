@@ -42,7 +42,7 @@ struct Layout {
       total;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
-  int64_t n_items[kLayouts] = {0, 0, 0}, n_dense = 0, scratch_elems = 0;
+  int64_t n_items[kLayouts] = {}, n_dense = 0, scratch_elems = 0;
   size_t tens_doubles = 0;
 };
 
@@ -307,7 +307,7 @@ int ridg_workspace_bytes(const ridg_problem* problem, size_t* bytes) {
   if (rc) return fail(rc, msg);
   Basis B = make_basis(P.d, P.M);
   RefTensors T = make_tensors(B);
-  int64_t n_items[kLayouts] = {0, 0, 0};
+  int64_t n_items[kLayouts] = {};
   RegionPlans R;
   if (P.solver == RIDG_SOLVER_REGION) {
     R = build_plans(P);
@@ -369,7 +369,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
       plan_flops += 2.0 * nt * nt;  // W_centre = alpha + B x
     }
   }
-  const int64_t n_items[kLayouts] = {(int64_t)items[0].size(), (int64_t)items[1].size(), (int64_t)items[2].size()};
+  int64_t n_items[kLayouts];
+  for (int l = 0; l < kLayouts; ++l) n_items[l] = (int64_t)items[l].size();
   h->L = make_layout(P, h->T, &R, n_items);
   if (ws_bytes < h->L.total) {
     delete h;
@@ -863,8 +864,8 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
       break;
     case RIDG_OPT_PLAN_LAYOUT:
       if (h->P.solver != RIDG_SOLVER_REGION && value) return fail(RIDG_E_UNSUPPORTED, "plan layout applies to REGION");
-      if (value == 2 && h->P.precision != RIDG_FP64)
-        return fail(RIDG_E_UNSUPPORTED, "the two-region layout is FP64 only");
+      if (value >= 2 && h->P.precision != RIDG_FP64)
+        return fail(RIDG_E_UNSUPPORTED, "plan layouts 2 and 3 are FP64 only");
       h->opt_layout = (int)value;
       break;
     case RIDG_OPT_FUSED:
@@ -921,7 +922,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   const bool pref = h->P.solver == RIDG_SOLVER_PREFACTORED;
   const bool fusable = pref && fused_fits(h->P.d, h->P.M, h->P.nel);
   for (int g = 0; g < 2; ++g)
-    for (int l = 0; l < (region ? (h->P.precision == RIDG_FP64 ? 3 : 2) : 1); ++l)
+    for (int l = 0; l < (region ? (h->P.precision == RIDG_FP64 ? kLayouts : 2) : 1); ++l)
       for (int c = 0; c < (pref ? 2 : 1); ++c) cands.push_back({g, l, 0, c});
   if (fusable) cands.push_back({0, 0, 1, 0});
   // keep the state: tuning steps run on a copy that is restored afterwards

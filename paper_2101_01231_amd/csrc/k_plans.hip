@@ -4,7 +4,7 @@
 namespace ridg {
 
 template <int D, int M, bool PADDED, bool F32 = false>
-__global__ __launch_bounds__(256) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg<D, M, PADDED>::MIN_WAVES))) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                             double* __restrict__ W, PlanTables t,
                                                             const PlanRec* __restrict__ plans,
                                                             const int32_t* __restrict__ items,
@@ -211,10 +211,118 @@ __global__ __launch_bounds__(256) void predict_plans2_kernel(DevGeom g, double d
   if (write[1]) W[(int64_t)k * nel + e[1]] = sw1[(nb - 1) * NT + k];
 }
 
+// Two rows per lane (PlanCfg2R): twice the regions per wavefront of the packed layout, each pivot
+// row read once for two rows. FP64; bitwise the results of the packed layout.
+template <int D, int M>
+__global__ __launch_bounds__(256) void predict_plans_2r_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+                                                               double* __restrict__ W, PlanTables t,
+                                                               const PlanRec* __restrict__ plans,
+                                                               const int32_t* __restrict__ items,
+                                                               const int32_t* __restrict__ item_plan,
+                                                               int64_t n_items) {
+  using C = PlanCfg2R<D, M>;
+  constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB, SEGW = C::SEGW;
+  __shared__ double s_w[C::WAVES][S][NB][NT];
+  __shared__ double s_piv[C::WAVES][S][2 * (NT + 2)];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const bool tail = lane >= S * SEGW;
+  const int seg = tail ? 0 : lane / SEGW;
+  const int k = tail ? lane - S * SEGW : lane % SEGW;
+  const bool idle[2] = {tail, tail || k + SEGW >= NT};
+  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S;
+  if (wave_first >= n_items) return;  // the list is padded to S
+  int addr[LB > 0 ? LB : 1];
+#pragma unroll
+  for (int r = 0; r < LB; ++r) addr[r] = 4 * (tail ? lane : seg * SEGW + (k + (1 << r)) % SEGW);
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  int32_t e = items[wave_first + seg];
+  const bool write = e >= 0 && !tail;
+  if (e < 0) e = -e - 1;
+  int base[3];
+  elem_idx(g, e, base);
+  const int pid = __builtin_amdgcn_readfirstlane(item_plan[wave_first]);
+  const PlanRec* pr = plans + pid;
+  const int nb = pr->nb;
+  double* sw = &s_w[wave][seg][0][0];
+  double* spiv = &s_piv[wave][seg][0];
+  int kr[2];
+  int ccl[2];
+  double ccv[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    kr[u] = idle[u] ? 0 : k + u * SEGW;
+    ccl[u] = t.cc_idx[kr[u]];
+    ccv[u] = t.cc_val[kr[u]];
+  }
+  for (int b = 0; b < nb; ++b) {
+    const PlanBlock blk = pr->blk[b];
+    int mask = 0;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+      mask |= ((blk.src[2 * i] == kOwn ? 1 : 0) | (blk.src[2 * i + 1] == kOwn ? 2 : 0)) << (2 * i);
+    const int gi[3] = {wrap(base[0] + blk.off[0], g.n0), wrap(base[1] + blk.off[1], g.n1),
+                       wrap(base[2] + blk.off[2], g.n2)};
+    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
+    double V0[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double v = g.a[i];
+#pragma unroll
+      for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
+      V0[i] = v * dt / geom_h(g, i);
+    }
+    double a[2][NT];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const double* a0 = t.A0 + ((size_t)mask * NT + kr[u]) * NT;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) a[u][l] = a0[l];
+    }
+#pragma unroll 1
+    for (int i = 0; i < D; ++i) {
+      const double vi = sel<D>(V0, i);
+      const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT) * NT;
+#pragma unroll
+      for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int l = 0; l < NT; ++l) a[u][l] = fma(vi, kk[(size_t)kr[u] * NT + l], a[u][l]);
+    }
+    double rhs[2] = {ccv[0] * Q[(int64_t)ccl[0] * nel + ge], ccv[1] * Q[(int64_t)ccl[1] * nel + ge]};
+#pragma unroll 1
+    for (int i = 0; i < D; ++i) {
+      const double vi = sel<D>(V0, i);
+#pragma unroll 1
+      for (int sd = 0; sd < 2; ++sd) {
+        const int src = blk.src[2 * i + sd];
+        if (src == kOwn) continue;
+        const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT) * NT;
+        const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT) * NT;
+        const double* wsrc = sw + src * NT;
+        double acc0 = 0.0, acc1 = 0.0;
+#pragma unroll
+        for (int l = 0; l < NT; ++l) {
+          const double w = wsrc[l];
+          acc0 = fma(fma(vi, f0[(size_t)kr[0] * NT + l], fc[(size_t)kr[0] * NT + l]), w, acc0);
+          acc1 = fma(fma(vi, f0[(size_t)kr[1] * NT + l], fc[(size_t)kr[1] * NT + l]), w, acc1);
+        }
+        rhs[0] -= acc0;
+        rhs[1] -= acc1;
+      }
+    }
+    seg_solve_2r<NT, LB, SEGW>(a, rhs, k, idle, addr, spiv, sw + b * NT);
+  }
+  if (write) {
+    W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
+    if (!idle[1]) W[(int64_t)(k + SEGW) * nel + e] = sw[(nb - 1) * NT + k + SEGW];
+  }
+}
+
 template <int D, int M>
 struct IpwL {
   static int run(int layout) {
     if (layout == 2) return 2 * PlanCfg<D, M, false>::S;
+    if (layout == 3) return PlanCfg2R<D, M>::S;
     return layout ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S;
   }
 };
@@ -243,6 +351,16 @@ struct PlansL {
                  const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
+    if (layout == 3) {
+      if (precision != RIDG_FP64) return (int)hipErrorInvalidValue;
+      using C = PlanCfg2R<D, M>;
+      const int64_t per_block = (int64_t)C::WAVES * C::S;
+      const int64_t blocks = (n_items + per_block - 1) / per_block;
+      if (blocks == 0) return 0;
+      hipLaunchKernelGGL((predict_plans_2r_kernel<D, M>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
+                         (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+      return (int)hipGetLastError();
+    }
     if (layout == 2) {
       if (precision != RIDG_FP64) return (int)hipErrorInvalidValue;
       using C = PlanCfg<D, M, false>;

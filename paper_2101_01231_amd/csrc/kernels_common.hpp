@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <type_traits>
 
 #include "ridg_internal.hpp"
 
@@ -109,6 +110,9 @@ struct PlanCfg {
   static constexpr int LB = SEGW <= 1 ? 0 : SEGW <= 2 ? 1 : SEGW <= 4 ? 2 : SEGW <= 8 ? 3 : SEGW <= 16 ? 4 : SEGW <= 32 ? 5 : 6;
   static constexpr int NB = D == 3 ? 8 : pow3(D);            // plan blocks (larger plans use the dense path)
   static constexpr int WAVES = 4;
+  // register budget hint (waves per SIMD): 2D order 4 (theta_T = 20) fits 128 VGPRs, i.e. four
+  // waves, with a few bytes of spill; elsewhere the compiler's own choice is kept
+  static constexpr int MIN_WAVES = (D == 2 && M == 4) ? 4 : 1;
 };
 
 // Segment-wide maximum of a 32-bit key (every lane of the segment ends with it).
@@ -152,6 +156,53 @@ __device__ inline double recip(double x) {
   return fma(r, e, r);
 }
 
+// Compile-time loop: f(std::integral_constant<int, I>) for I = B..E-1.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+__device__ __forceinline__ unsigned lds_addr(const double* p) {
+  return (unsigned)(size_t)(const __attribute__((address_space(3))) double*)p;
+}
+
+// LDS stores at compile-time double offsets from a per-lane base. Two values per ds_write2_b64,
+// each from its own register pair, so nothing is copied into consecutive registers first (the
+// compiler would pair them into ds_write_b128 and insert the copies).
+template <int O0, int O1>
+__device__ __forceinline__ void lds_store2(unsigned base, double x, double y) {
+  asm volatile("ds_write2_b64 %0, %1, %2 offset0:%3 offset1:%4" : : "v"(base), "v"(x), "v"(y), "i"(O0), "i"(O1)
+               : "memory");
+}
+template <int O>
+__device__ __forceinline__ void lds_store1(unsigned base, double x) {
+  asm volatile("ds_write_b64 %0, %1 offset:%2" : : "v"(base), "v"(x), "i"(O * 8) : "memory");
+}
+
+// Publish a[J0..NT-1], rhs and inv at doubles OFF + J0 .. OFF + NT + 1 of the buffer at base.
+template <int J, int NT>
+__device__ __forceinline__ double row_val(const double (&a)[NT], double rhs, double inv) {
+  if constexpr (J < NT)
+    return a[J];
+  else if constexpr (J == NT)
+    return rhs;
+  else
+    return inv;
+}
+template <int OFF, int J0, int NT>
+__device__ __forceinline__ void publish_row(unsigned base, const double (&a)[NT], double rhs, double inv) {
+  constexpr int E = NT + 2;
+  constexpr int NP = (E - J0) / 2;
+  static_for<0, NP>([&](auto P) {
+    constexpr int j = J0 + 2 * decltype(P)::value;
+    lds_store2<OFF + j, OFF + j + 1>(base, row_val<j, NT>(a, rhs, inv), row_val<j + 1, NT>(a, rhs, inv));
+  });
+  if constexpr ((E - J0) & 1) lds_store1<OFF + E - 1>(base, row_val<E - 1, NT>(a, rhs, inv));
+}
+
 // Gauss-Jordan elimination with partial pivoting of [A | b], row k of A in lane k of the segment.
 // The pivot of column c is the unused row of largest |a_c|, compared on a 32-bit key (the FP32
 // image of |a_c| with its low bits replaced by the row, ties to the lowest row). The pivot row,
@@ -163,12 +214,15 @@ __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle,
                                  double* piv, double* x) {
   constexpr unsigned LMASK = (1u << LB) - 1u;
   constexpr int PS = NT + 2;  // published row: a[c+1..NT-1], rhs, 1/pivot
+  static_assert(2 * PS <= 256, "ds_write2_b64 offsets are 8-bit");
   bool used = idle;
   int mystep = -1;
   double myinv = 0.0;
-#pragma unroll
-  for (int c = 0; c < NT; ++c) {
-    double* pv = piv + (c & 1) * PS;
+  const unsigned pbase = lds_addr(piv);
+  static_for<0, NT>([&](auto C) {
+    constexpr int c = decltype(C)::value;
+    constexpr int off = (c & 1) * PS;
+    const double* pv = piv + off;
     unsigned key = 0u;
     if (!used) key = (__float_as_uint((float)fabs(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
     if constexpr (POW2)
@@ -179,12 +233,7 @@ __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle,
     const bool is_piv = (k == p) && !idle;
     if (is_piv) {
       myinv = recip(a[c]);
-      // one 64-bit store per value: lets the register allocator keep a[] in place
-      volatile __attribute__((address_space(3))) double* vp = (volatile __attribute__((address_space(3))) double*)pv;
-#pragma unroll
-      for (int j = c + 1; j < NT; ++j) vp[j] = a[j];
-      vp[NT] = rhs;
-      vp[NT + 1] = myinv;
+      publish_row<off, c + 1, NT>(pbase, a, rhs, myinv);
       used = true;
       mystep = c;
     }
@@ -195,8 +244,79 @@ __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle,
       for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, pv[j], a[j]);
       rhs = fma(-l, pv[NT], rhs);
     }
-  }
+  });
   if (mystep >= 0) x[mystep] = rhs * myinv;
+  wave_sync();
+}
+
+// Segment geometry with two rows per lane: rows k and k + SEGW of a theta_T-row system live in lane
+// k of a SEGW = ceil(theta_T / 2)-lane segment. Row numbers, hence pivot keys, are those of the
+// one-row layout, so both eliminate in the same order with the same arithmetic.
+template <int D, int M>
+struct PlanCfg2R {
+  static constexpr int NS = n_space(D, M);
+  static constexpr int NT = n_spacetime(D, M);
+  static constexpr int SEGW = (NT + 1) / 2;
+  static constexpr int S = 64 / SEGW;
+  static constexpr int LB = SEGW <= 1 ? 0 : SEGW <= 2 ? 1 : SEGW <= 4 ? 2 : SEGW <= 8 ? 3 : SEGW <= 16 ? 4 : SEGW <= 32 ? 5 : 6;
+  static constexpr int NB = D == 3 ? 8 : pow3(D);
+  static constexpr int WAVES = 4;
+};
+
+// Gauss-Jordan with partial pivoting as seg_solve, each lane holding two rows: one read of the
+// published pivot row updates both (half the LDS traffic of one row per lane).
+template <int NT, int LB, int SEGW>
+__device__ inline void seg_solve_2r(double (&a)[2][NT], double (&rhs)[2], int k, const bool (&idle)[2],
+                                    const int (&addr)[LB > 0 ? LB : 1], double* piv, double* x) {
+  constexpr unsigned LMASK = (2u << LB) - 1u;  // row numbers 0 .. 2 SEGW - 1
+  constexpr int PS = NT + 2;
+  static_assert(2 * PS <= 256, "ds_write2_b64 offsets are 8-bit");
+  bool used[2] = {idle[0], idle[1]};
+  int step[2] = {-1, -1};
+  double inv[2] = {0.0, 0.0};
+  const unsigned pbase = lds_addr(piv);
+  static_for<0, NT>([&](auto C) {
+    constexpr int c = decltype(C)::value;
+    constexpr int off = (c & 1) * PS;
+    const double* pv = piv + off;
+    unsigned key = 0u;
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (!used[u])
+        key = max(key, (__float_as_uint((float)fabs(a[u][c])) & ~LMASK) | (LMASK - (unsigned)(k + u * SEGW)));
+    key = seg_max_rot<SEGW, LB>(key, addr);
+    const int p = (int)(LMASK - (key & LMASK));
+    const bool piv0 = (p == k) && !idle[0];
+    const bool piv1 = (p == k + SEGW) && !idle[1];
+    if (piv0) {
+      inv[0] = recip(a[0][c]);
+      publish_row<off, c + 1, NT>(pbase, a[0], rhs[0], inv[0]);
+      used[0] = true;
+      step[0] = c;
+    }
+    if (piv1) {
+      inv[1] = recip(a[1][c]);
+      publish_row<off, c + 1, NT>(pbase, a[1], rhs[1], inv[1]);
+      used[1] = true;
+      step[1] = c;
+    }
+    wave_sync();
+    // every row but the pivot row (and idle rows) is reduced; a zero multiplier leaves a row as is
+    const double ip = pv[NT + 1];
+    const double l0 = (piv0 || idle[0]) ? 0.0 : a[0][c] * ip;
+    const double l1 = (piv1 || idle[1]) ? 0.0 : a[1][c] * ip;
+#pragma unroll
+    for (int j = c + 1; j < NT; ++j) {
+      const double v = pv[j];
+      a[0][j] = fma(-l0, v, a[0][j]);
+      a[1][j] = fma(-l1, v, a[1][j]);
+    }
+    const double pr = pv[NT];
+    rhs[0] = fma(-l0, pr, rhs[0]);
+    rhs[1] = fma(-l1, pr, rhs[1]);
+  });
+  if (step[0] >= 0) x[step[0]] = rhs[0] * inv[0];
+  if (step[1] >= 0) x[step[1]] = rhs[1] * inv[1];
   wave_sync();
 }
 

@@ -225,7 +225,9 @@ int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in
 int launch_predict_plans(int d, int M, int layout, int precision, int refine, const DevGeom& g, double dt,
                          const double* Q, double* W, const PlanTables& t, const PlanRec* plans,
                          const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
-constexpr int kLayouts = 3;  // plan-kernel segment layouts: 0 packed, 1 padded to a power of two, 2 two regions per packed segment
+// plan-kernel segment layouts: 0 packed, 1 padded to a power of two, 2 two regions per packed
+// segment, 3 two rows per lane
+constexpr int kLayouts = 4;
 int items_per_wave(int d, int M, int layout);  // work-list padding multiple (regions a wavefront takes at once)
 // Whole run of n_steps on one workgroup (mesh state resident in LDS), constant velocity;
 // returns hipErrorInvalidValue when the mesh does not fit.
