@@ -13,6 +13,9 @@ a bounded sample of the same workload.
 """
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -28,6 +31,119 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop (F
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # published FP32 vector peak (counts packed FP32, which this build does not use)
 HBM_PEAK_GBS = 8000.0
 METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error; p99 latency"
+
+
+# translation unit of each kernel family: a counter record is valid while these sources are unchanged
+KERNEL_UNITS = {"predict_plans2_kernel": "k_plans.hip", "predict_plans_2r_kernel": "k_plans.hip",
+                "predict_plans_kernel": "k_plans.hip",
+                "predict_prefactored_kernel": "k_prefactored.hip", "tap_update_kernel": "k_prefactored.hip",
+                "fused_prefactored_kernel": "k_prefactored.hip", "correct_kernel": "k_correct.hip",
+                "predict_tear_kernel": "k_tear_dense.hip", "predict_dense_kernel": "k_tear_dense.hip",
+                "batch_predict_kernel": "k_batch.hip", "batch_correct_kernel": "k_batch.hip"}
+RECORD_TAG = "traffic-record: "
+
+
+def kernel_source_hash(kernel):
+    """sha256 of the sources a kernel is compiled from (its unit and the shared device headers)."""
+    fam = next((f for f in KERNEL_UNITS if f + "<" in kernel), None)
+    if fam is None:
+        return None
+    h = hashlib.sha256()
+    for f in (KERNEL_UNITS[fam], "kernels_common.hpp", "ridg_internal.hpp"):
+        with open(os.path.join(HERE, "paper_2101_01231_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def dominant_kernel(info, opts, precision):
+    """Name (as the profiler prints it) of the kernel that runs the prediction stage."""
+    from paper_2101_01231_amd import ridg
+    d, M = _dim_order(info)
+    if info.solver == ridg.SOLVER_PREFACTORED:
+        if opts.get("composite"):
+            return f"ridg::tap_update_kernel<{d}, {info.theta}, {info.theta}>"
+        return f"ridg::predict_prefactored_kernel<{d}, {M}>"
+    if info.solver == ridg.SOLVER_REGION:
+        lay = opts.get("plan_layout", 0)
+        if lay == 2:
+            return f"ridg::predict_plans2_kernel<{d}, {M}>"
+        if lay == 3:
+            return f"ridg::predict_plans_2r_kernel<{d}, {M}>"
+        f32 = "true" if precision == "fp32" else "false"
+        return f"ridg::predict_plans_kernel<{d}, {M}, {'true' if lay == 1 else 'false'}, {f32}>"
+    return f"ridg::predict_dense_kernel<{d}, {M}"
+
+
+def _dim_order(info):
+    """(d, M) from the basis sizes theta = C(M-1+d, d) and theta_T = C(M+d, d+1)."""
+    for d in (1, 2, 3):
+        for M in range(1, 9):
+            if math.comb(M - 1 + d, d) == info.theta and math.comb(M + d, d + 1) == info.theta_t:
+                return d, M
+    raise ValueError("unknown basis size")
+
+
+def traffic_from_profiles(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summaries, or None when no
+    record exists or the kernel's sources changed since the counters were taken."""
+    want = kernel_source_hash(kernel)
+    for path in sorted(glob.glob(os.path.join(HERE, "profiles", "*.md"))):
+        with open(path) as fh:
+            for line in fh:
+                if not line.startswith(RECORD_TAG):
+                    continue
+                rec = json.loads(line[len(RECORD_TAG):])
+                if rec["kernel"].startswith(kernel) and rec["src"] == want:
+                    return {"bytes": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
+                            "write_bytes": rec["write_bytes"], "source": os.path.basename(path)}
+    return None
+
+
+def _counter_means(csv_path, counter):
+    sums, counts = {}, {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            k = r["Kernel_Name"]
+            sums[k] = sums.get(k, 0.0) + float(r["Counter_Value"])
+            counts[k] = counts.get(k, 0) + 1
+    return {k: (sums[k] / counts[k], counts[k]) for k in sums}
+
+
+def counter_summary(args):
+    """Markdown summary of FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), each scaled by what the
+    same counter reads for the calibration copy (bench.py --workload copy) of known size."""
+    fetch_csv, write_csv, cfetch_csv, cwrite_csv = args.counter_summary
+    copy_bytes = 256 << 20
+    cf = max(_counter_means(cfetch_csv, "FETCH_SIZE").values(), key=lambda x: x[0])[0]
+    cw = max(_counter_means(cwrite_csv, "WRITE_SIZE").values(), key=lambda x: x[0])[0]
+    ff, fw = copy_bytes / (cf * 1024.0), copy_bytes / (cw * 1024.0)
+    fetch = _counter_means(fetch_csv, "FETCH_SIZE")
+    write = _counter_means(write_csv, "WRITE_SIZE")
+    lines = [f"# HBM traffic per dispatch: {args.title}", "",
+             "Counters: `FETCH_SIZE` and `WRITE_SIZE` (KiB per dispatch), one rocprofv3 run each. Calibration: "
+             f"the copy kernel moves {copy_bytes >> 20} MiB each way and reads FETCH_SIZE {cf:.0f} KiB, "
+             f"WRITE_SIZE {cw:.0f} KiB, so bytes = FETCH_SIZE x {ff * 1024:.1f} and WRITE_SIZE x {fw * 1024:.1f}.", "",
+             "Commands (repo root, `cd /tmp && export TMPDIR=/tmp` first):", "", "```"]
+    lines += args.commands.split(";;")
+    lines += ["```", "", "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | fetch MB | write MB |",
+              "|---|---|---|---|---|---|"]
+    recs = []
+    for k in sorted(fetch, key=lambda x: -fetch[x][0]):
+        if "ridg::" not in k or k not in write:
+            continue
+        name = k.replace("void ", "", 1)
+        name = name[:name.index("(")] if "(" in name else name
+        fb, wb = fetch[k][0] * 1024.0 * ff, write[k][0] * 1024.0 * fw
+        lines.append(f"| `{name}` | {fetch[k][1]} | {fetch[k][0]:.0f} | {write[k][0]:.0f} | {fb / 1e6:.1f} | "
+                     f"{wb / 1e6:.1f} |")
+        src = kernel_source_hash(name)
+        if src:
+            recs.append(RECORD_TAG + json.dumps({"kernel": name, "src": src, "fetch_bytes": round(fb),
+                                                 "write_bytes": round(wb), "dispatches": fetch[k][1]}))
+    lines += ["", "Records read by bench.py (kernel, hash of its sources, bytes per dispatch):", ""] + recs
+    print("\n".join(lines))
 
 
 def workload(name):
@@ -82,7 +198,7 @@ def cpu_baseline(wl, target_s):
         S.step_sampled(prob, wl.q0, wl.dt, els)
         el = time.perf_counter() - t0
         elapsed, done = el, len(els)
-        if el * 4 > target_s or side >= min(wl.n):
+        if el * 4 > 2 * target_s or side >= min(wl.n):
             break
         side *= 2
     rate = done * prob.theta_t / elapsed
@@ -200,7 +316,13 @@ def main():
     ap.add_argument("--requests", type=int, default=200, help="serving: number of requests")
     ap.add_argument("--time-scale", type=float, default=1.0, help="serving: arrival clock speed-up")
     ap.add_argument("--mem-gb", type=float, default=64.0, help="serving: device memory budget")
+    ap.add_argument("--counter-summary", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV"),
+                    help="print the HBM-traffic summary of rocprofv3 counter runs (no GPU needed)")
+    ap.add_argument("--title", default="", help="counter summary: workload description")
+    ap.add_argument("--commands", default="", help="counter summary: the profiler commands, ';;'-separated")
     args = ap.parse_args()
+    if args.counter_summary:
+        return counter_summary(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
@@ -238,6 +360,12 @@ def main():
                 "correction": {"achieved_tflops": info.flops_correct / (R["corr_ms"] * 1e-3) / 1e12,
                                "achieved_gbs": info.bytes_correct / (R["corr_ms"] * 1e-3) / 1e9,
                                "avg_ms": R["corr_ms"]}}
+    kern_name = dominant_kernel(info, R["opts"], best)
+    tr = traffic_from_profiles(kern_name)
+    roofline["kernel_name"] = kern_name
+    roofline["traffic"] = tr["bytes"] if tr else None
+    if tr:
+        roofline["traffic_detail"] = tr
     if info.solver == ridg.SOLVER_PREFACTORED:
         comp = R["opts"]["composite"]
         nbytes = info.bytes_composite if comp else info.bytes_predict
