@@ -3,6 +3,8 @@
 
 namespace ridg {
 
+constexpr int kLoadChunk = 4;  // table loads between scheduling barriers (two-rows-per-lane kernel)
+
 template <int D, int M, bool PADDED, bool F32 = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg<D, M, PADDED>::MIN_WAVES))) void predict_plans_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                             double* __restrict__ W, PlanTables t,
@@ -212,9 +214,11 @@ __global__ __launch_bounds__(256) void predict_plans2_kernel(DevGeom g, double d
 }
 
 // Two rows per lane (PlanCfg2R): twice the regions per wavefront of the packed layout, each pivot
-// row read once for two rows. FP64; bitwise the results of the packed layout.
+// row read once for two rows. FP64; bitwise the results of the packed layout. Table rows are
+// addressed by 32-bit byte offsets and loaded kLoadChunk at a time (scheduling barriers), which
+// keeps the loads in flight, and with them the register count, bounded.
 template <int D, int M>
-__global__ __launch_bounds__(256) void predict_plans_2r_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D, M>::MIN_WAVES))) void predict_plans_2r_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                                double* __restrict__ W, PlanTables t,
                                                                const PlanRec* __restrict__ plans,
                                                                const int32_t* __restrict__ items,
@@ -247,11 +251,13 @@ __global__ __launch_bounds__(256) void predict_plans_2r_kernel(DevGeom g, double
   double* sw = &s_w[wave][seg][0][0];
   double* spiv = &s_piv[wave][seg][0];
   int kr[2];
+  unsigned rb[2];  // byte offset of row kr within a theta_T x theta_T table
   int ccl[2];
   double ccv[2];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     kr[u] = idle[u] ? 0 : k + u * SEGW;
+    rb[u] = (unsigned)kr[u] * (unsigned)(NT * 8);
     ccl[u] = t.cc_idx[kr[u]];
     ccv[u] = t.cc_val[kr[u]];
   }
@@ -273,20 +279,24 @@ __global__ __launch_bounds__(256) void predict_plans_2r_kernel(DevGeom g, double
       V0[i] = v * dt / geom_h(g, i);
     }
     double a[2][NT];
+    {
+      const char* a0 = (const char*)t.A0 + (unsigned)mask * (unsigned)(NT * NT * 8);
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const double* a0 = t.A0 + ((size_t)mask * NT + kr[u]) * NT;
+      for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int l = 0; l < NT; ++l) a[u][l] = a0[l];
+        for (int l = 0; l < NT; ++l) a[u][l] = *(const double*)(a0 + (rb[u] + (unsigned)(l * 8)));
     }
 #pragma unroll 1
     for (int i = 0; i < D; ++i) {
       const double vi = sel<D>(V0, i);
-      const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT) * NT;
+      const char* kk = (const char*)t.K + (unsigned)(i * 4 + ((mask >> (2 * i)) & 3)) * (unsigned)(NT * NT * 8);
 #pragma unroll
       for (int u = 0; u < 2; ++u)
 #pragma unroll
-        for (int l = 0; l < NT; ++l) a[u][l] = fma(vi, kk[(size_t)kr[u] * NT + l], a[u][l]);
+        for (int l = 0; l < NT; ++l) {
+          a[u][l] = fma(vi, *(const double*)(kk + (rb[u] + (unsigned)(l * 8))), a[u][l]);
+          if (l % kLoadChunk == kLoadChunk - 1) __builtin_amdgcn_sched_barrier(0);
+        }
     }
     double rhs[2] = {ccv[0] * Q[(int64_t)ccl[0] * nel + ge], ccv[1] * Q[(int64_t)ccl[1] * nel + ge]};
 #pragma unroll 1
@@ -296,15 +306,18 @@ __global__ __launch_bounds__(256) void predict_plans_2r_kernel(DevGeom g, double
       for (int sd = 0; sd < 2; ++sd) {
         const int src = blk.src[2 * i + sd];
         if (src == kOwn) continue;
-        const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT) * NT;
-        const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT) * NT;
+        const unsigned toff = (unsigned)(i * 2 + sd) * (unsigned)(NT * NT * 8);
+        const char* f0 = (const char*)t.Fn0 + toff;
+        const char* fc = (const char*)t.FnC + toff;
         const double* wsrc = sw + src * NT;
         double acc0 = 0.0, acc1 = 0.0;
 #pragma unroll
         for (int l = 0; l < NT; ++l) {
           const double w = wsrc[l];
-          acc0 = fma(fma(vi, f0[(size_t)kr[0] * NT + l], fc[(size_t)kr[0] * NT + l]), w, acc0);
-          acc1 = fma(fma(vi, f0[(size_t)kr[1] * NT + l], fc[(size_t)kr[1] * NT + l]), w, acc1);
+          const unsigned o0 = rb[0] + (unsigned)(l * 8), o1 = rb[1] + (unsigned)(l * 8);
+          acc0 = fma(fma(vi, *(const double*)(f0 + o0), *(const double*)(fc + o0)), w, acc0);
+          acc1 = fma(fma(vi, *(const double*)(f0 + o1), *(const double*)(fc + o1)), w, acc1);
+          if (l % kLoadChunk == kLoadChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
         rhs[0] -= acc0;
         rhs[1] -= acc1;

@@ -261,6 +261,8 @@ struct PlanCfg2R {
   static constexpr int LB = SEGW <= 1 ? 0 : SEGW <= 2 ? 1 : SEGW <= 4 ? 2 : SEGW <= 8 ? 3 : SEGW <= 16 ? 4 : SEGW <= 32 ? 5 : 6;
   static constexpr int NB = D == 3 ? 8 : pow3(D);
   static constexpr int WAVES = 4;
+  // register budget hint: 2D order 4 at three waves per SIMD (168 VGPRs, a few spilled) beats two
+  static constexpr int MIN_WAVES = (D == 2 && M == 4) ? 3 : 1;
 };
 
 // Gauss-Jordan with partial pivoting as seg_solve, each lane holding two rows: one read of the
