@@ -38,7 +38,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, dc, kc, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
+  size_t q0, q1, w, stage, tens, g, dc, kc, fg, fd, fk, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
       total;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
@@ -93,6 +93,12 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
   L.g = take((size_t)kMaxBlocks * nt * ns * 8);
   L.dc = take((size_t)7 * ns * nt * 8);
   L.kc = take((size_t)kMaxTapUpdate * ns * ns * 8);
+  {  // MFMA fragments of the constant-velocity operators (G, D, K)
+    const bool pref = P.solver == RIDG_SOLVER_PREFACTORED;
+    L.fg = take(pref ? mfma_fragment_doubles(kMaxBlocks, (int)nt, (int)ns) * 8 : 8);
+    L.fd = take(pref ? mfma_fragment_doubles(7, (int)ns, (int)nt) * 8 : 8);
+    L.fk = take(pref ? mfma_fragment_doubles(kMaxTapUpdate, (int)ns, (int)ns) * 8 : 8);
+  }
   L.taps = take((size_t)kMaxBlocks * 3 * 4);
   int64_t n_dense = 0;
   size_t nplans = 0;
@@ -148,6 +154,10 @@ struct ridg_handle {
   std::vector<int32_t> host_taps;
   double* Dc = nullptr;  // constant-velocity correction taps
   double* Kc = nullptr;  // composite prediction+correction taps
+  double* Fg = nullptr;  // MFMA fragments of G, Dc and Kc
+  double* Fd = nullptr;
+  double* Fk = nullptr;
+  int opt_mfma = 0;
   std::vector<int32_t> host_dtaps, host_ktaps;
   int opt_composite = 0;
   int n_dtaps = 0;
@@ -247,7 +257,7 @@ std::pair<double, double> flops_model(const ridg_handle* h, double plan_flops) {
 // ---------------------------------------------------------------- autotuner
 namespace {
 std::mutex g_tune_mu;
-std::map<std::string, std::array<int, 4>> g_tune_cache;  // problem key -> {graph, layout, fused, composite}
+std::map<std::string, std::array<int, 5>> g_tune_cache;  // problem key -> {graph, layout, fused, composite, mfma}
 bool g_tune_file_loaded = false;
 
 std::string tune_key(const ridg_handle* h, int32_t steps) {
@@ -265,18 +275,22 @@ void tune_file_load() {
   if (!path) return;
   FILE* f = std::fopen(path, "r");
   if (!f) return;
-  char key[200];
-  int a, b, c, e;
-  while (std::fscanf(f, "%199s %d %d %d %d", key, &a, &b, &c, &e) == 5) g_tune_cache[key] = {a, b, c, e};
+  char line[512];
+  while (std::fgets(line, sizeof(line), f)) {  // "<key> graph layout fused composite mfma"
+    char key[256];
+    int o[5], extra;
+    if (std::sscanf(line, "%255s %d %d %d %d %d %d", key, &o[0], &o[1], &o[2], &o[3], &o[4], &extra) == 6)
+      g_tune_cache[key] = {o[0], o[1], o[2], o[3], o[4]};
+  }
   std::fclose(f);
 }
 
-void tune_file_append(const std::string& key, const std::array<int, 4>& o) {
+void tune_file_append(const std::string& key, const std::array<int, 5>& o) {
   const char* path = std::getenv("RIDG_AUTOTUNE_CACHE");
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d\n", key.c_str(), o[0], o[1], o[2], o[3]);
+  std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o[0], o[1], o[2], o[3], o[4]);
   std::fclose(f);
 }
 }  // namespace
@@ -385,6 +399,9 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->G = (double*)(h->ws + h->L.g);
   h->Dc = (double*)(h->ws + h->L.dc);
   h->Kc = (double*)(h->ws + h->L.kc);
+  h->Fg = (double*)(h->ws + h->L.fg);
+  h->Fd = (double*)(h->ws + h->L.fd);
+  h->Fk = (double*)(h->ws + h->L.fk);
   h->taps = (int32_t*)(h->ws + h->L.taps);
   h->plans = (PlanRec*)(h->ws + h->L.plans);
   for (int l = 0; l < kLayouts; ++l) {
@@ -621,9 +638,16 @@ static int ensure_dt_tables(ridg_t* h, double dt) {
   };
   flat(dc, &h->host_dtaps);
   flat(kc, &h->host_ktaps);
+  const int nt = h->T.nt, ns = h->T.ns;
+  const std::vector<double> fg = mfma_fragments(pf.G.data(), (int)pf.offs.size(), nt, ns);
+  const std::vector<double> fd = mfma_fragments(dc.A.data(), (int)dc.offs.size(), ns, nt);
+  const std::vector<double> fk = mfma_fragments(kc.A.data(), (int)kc.offs.size(), ns, ns);
   int err = hipMemcpyAsync(h->G, pf.G.data(), pf.G.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Dc, dc.A.data(), dc.A.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Kc, kc.A.data(), kc.A.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipMemcpyAsync(h->Fg, fg.data(), fg.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipMemcpyAsync(h->Fd, fd.data(), fd.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipMemcpyAsync(h->Fk, fk.data(), fk.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipStreamSynchronize(h->stream);
   if (err) return hip_fail(err, "upload of the prefactored operators");
   h->g_dt = dt;
@@ -679,10 +703,22 @@ static int direct_step(ridg_t* h, double dt) {
     int err = record_event(h);
     if (err) return hip_fail(err, "timing event");
   }
+  const int nk = (int)h->host_ktaps.size() / 3, nd = (int)h->host_dtaps.size() / 3;
+  const int ns = h->T.ns, nt = h->T.nt;
+  // MFMA kernels stage the operator's fragments in LDS: operators too large for it stay on the VALU kernels
+  auto fits = [](int ntaps, int rows, int cols) { return mfma_fragment_doubles(ntaps, rows, cols) * 8 <= kMfmaMaxLds; };
+  const bool mfma_k = h->opt_mfma && fits(nk, ns, ns);
+  const bool mfma_pc = h->opt_mfma && fits(h->ntaps, nt, ns) && fits(nd, ns, nt);
   if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
-    int err = launch_tap_update(P.d, P.M, 1, h->geom, h->Q[h->cur], h->Q[h->cur], h->Q[1 - h->cur], h->Kc,
-                                h->host_ktaps.data(), (int)h->host_ktaps.size() / 3, h->stream);
+    int err = mfma_k ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
+                                            h->Q[1 - h->cur], h->Fk, h->host_ktaps.data(), nk, h->stream)
+                          : launch_tap_update(P.d, P.M, 1, h->geom, h->Q[h->cur], h->Q[h->cur], h->Q[1 - h->cur],
+                                              h->Kc, h->host_ktaps.data(), nk, h->stream);
     if (err) return hip_fail(err, "composite launch");
+  } else if (pref && mfma_pc) {
+    int err = launch_tap_mfma(P.d, P.M, kMfmaPredict, h->geom, h->Q[h->cur], nullptr, h->W, h->Fg,
+                              h->host_taps.data(), h->ntaps, h->stream);
+    if (err) return hip_fail(err, "prediction launch");
   } else {
     int rc = run_predict(h, h->Q[h->cur], dt);
     if (rc) return rc;
@@ -692,9 +728,12 @@ static int direct_step(ridg_t* h, double dt) {
     if (err) return hip_fail(err, "timing event");
   }
   int err = 0;
-  if (pref && !h->opt_composite)
+  if (pref && !h->opt_composite && mfma_pc)
+    err = launch_tap_mfma(P.d, P.M, kMfmaCorrect, h->geom, h->W, h->Q[h->cur], h->Q[1 - h->cur], h->Fd,
+                          h->host_dtaps.data(), nd, h->stream);
+  else if (pref && !h->opt_composite)
     err = launch_tap_update(P.d, P.M, 0, h->geom, h->W, h->Q[h->cur], h->Q[1 - h->cur], h->Dc, h->host_dtaps.data(),
-                            (int)h->host_dtaps.size() / 3, h->stream);
+                            nd, h->stream);
   else if (!pref)
     err = launch_correct(P.d, P.M, P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt, h->stream);
   if (err) return hip_fail(err, "correction launch");
@@ -878,6 +917,11 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
         return fail(RIDG_E_UNSUPPORTED, "the composite stencil needs the PREFACTORED solver");
       h->opt_composite = (int)value;
       break;
+    case RIDG_OPT_MFMA:
+      if (value && h->P.solver != RIDG_SOLVER_PREFACTORED)
+        return fail(RIDG_E_UNSUPPORTED, "the MFMA tap kernels need the PREFACTORED solver");
+      h->opt_mfma = (int)value;
+      break;
     default:
       return fail(RIDG_E_INVAL, "unknown option");
   }
@@ -892,6 +936,7 @@ int ridg_get_option(ridg_t* h, int32_t option, int64_t* value) {
     case RIDG_OPT_PLAN_LAYOUT: *value = h->opt_layout; return RIDG_OK;
     case RIDG_OPT_FUSED: *value = h->opt_fused; return RIDG_OK;
     case RIDG_OPT_COMPOSITE: *value = h->opt_composite; return RIDG_OK;
+    case RIDG_OPT_MFMA: *value = h->opt_mfma; return RIDG_OK;
     default: return fail(RIDG_E_INVAL, "unknown option");
   }
 }
@@ -912,19 +957,21 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
       h->opt_layout = it->second[1];
       h->opt_fused = it->second[2];
       h->opt_composite = it->second[3];
+      h->opt_mfma = it->second[4];
       drop_graphs(h);
       if (best_ms_per_step) *best_ms_per_step = -1.0;  // from the cache, not re-measured
       return RIDG_OK;
     }
   }
-  std::vector<std::array<int, 4>> cands;
+  std::vector<std::array<int, 5>> cands;
   const bool region = h->P.solver == RIDG_SOLVER_REGION;
   const bool pref = h->P.solver == RIDG_SOLVER_PREFACTORED;
   const bool fusable = pref && fused_fits(h->P.d, h->P.M, h->P.nel);
   for (int g = 0; g < 2; ++g)
     for (int l = 0; l < (region ? (h->P.precision == RIDG_FP64 ? kLayouts : 2) : 1); ++l)
-      for (int c = 0; c < (pref ? 2 : 1); ++c) cands.push_back({g, l, 0, c});
-  if (fusable) cands.push_back({0, 0, 1, 0});
+      for (int c = 0; c < (pref ? 2 : 1); ++c)
+        for (int m = 0; m < (pref ? 2 : 1); ++m) cands.push_back({g, l, 0, c, m});
+  if (fusable) cands.push_back({0, 0, 1, 0, 0});
   // keep the state: tuning steps run on a copy that is restored afterwards
   const size_t bytes = (size_t)h->P.nel * h->T.ns * 8;
   const int cur0 = h->cur;
@@ -933,13 +980,14 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   if (!err) err = hipEventCreate(&e0);
   if (!err) err = hipEventCreate(&e1);
   double best = 1e300;
-  std::array<int, 4> pick = {h->opt_graph, h->opt_layout, h->opt_fused, h->opt_composite};
+  std::array<int, 5> pick = {h->opt_graph, h->opt_layout, h->opt_fused, h->opt_composite, h->opt_mfma};
   int rc = RIDG_OK;
   for (size_t c = 0; c < cands.size() && !err && !rc; ++c) {
     h->opt_graph = cands[c][0];
     h->opt_layout = cands[c][1];
     h->opt_fused = cands[c][2];
     h->opt_composite = cands[c][3];
+    h->opt_mfma = cands[c][4];
     drop_graphs(h);
     rc = ridg_step(h, 2, dt);  // warm-up (and graph capture)
     if (rc < 0) break;
@@ -965,6 +1013,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   h->opt_layout = pick[1];
   h->opt_fused = pick[2];
   h->opt_composite = pick[3];
+  h->opt_mfma = pick[4];
   drop_graphs(h);
   if (rc < 0) return rc;
   if (err) return hip_fail(err, "autotune");

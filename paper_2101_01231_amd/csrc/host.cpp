@@ -838,6 +838,20 @@ void build_correction_taps(const Problem& P, const RefTensors& T, double dt, Tap
   }
 }
 
+std::vector<double> mfma_fragments(const double* A, int ntaps, int rows, int cols) {
+  const int mt_n = (rows + 15) / 16, cq_n = (cols + 3) / 4;
+  std::vector<double> f(mfma_fragment_doubles(ntaps, rows, cols), 0.0);
+  size_t at = 0;
+  for (int mt = 0; mt < mt_n; ++mt)
+    for (int t = 0; t < ntaps; ++t)
+      for (int q = 0; q < cq_n; ++q)
+        for (int lane = 0; lane < 64; ++lane, ++at) {
+          const int r = 16 * mt + lane % 16, c = 4 * q + lane / 16;
+          if (r < rows && c < cols) f[at] = A[((size_t)t * rows + r) * cols + c];
+        }
+  return f;
+}
+
 void build_composite(const Problem& P, const Prefactored& G, const TapOperator& Dc, TapOperator* out) {
   (void)P;
   const int ns = Dc.rows, nt = Dc.cols;

@@ -1,0 +1,128 @@
+// Constant-velocity tap operators on the matrix cores (FP64 MFMA): the prefactored prediction
+// W = sum_s G_s Q_{e+s} (Sec. 2.2), the correction Q' = Q + sum_t D_t W_{e+t} (Sec. 2.3) and their
+// composition are one stacked-right-hand-side product each,
+//
+//   out[R x N] = base + [A_0 | A_1 | ... ] (R x ntaps*C) . [in_{e+off_0} ; in_{e+off_1} ; ...] (ntaps*C x N),
+//
+// with N the elements. A wavefront computes a 16-element column tile with v_mfma_f64_16x16x4f64:
+// rows of A in 16-row tiles, K in chunks of 4 columns of one tap (C padded to a multiple of 4 per
+// tap, so a chunk never straddles two taps and each lane needs one neighbour index per tap).
+//
+// Lane layout of v_mfma_f64_16x16x4f64 (A 16x4, B 4x16, D 16x16): lane l holds A[l % 16][l / 16],
+// B[l / 16][l % 16] and D[4 r + l / 16][l % 16] in its r-th result register, r = 0..3.
+//
+// The A fragments are precomputed on the host in exactly that order ([row tile][tap][chunk][lane])
+// and staged once per workgroup in LDS; each workgroup then sweeps a contiguous range of tiles,
+// so consecutive workgroups (spread over the XCDs) work on distant parts of the mesh while the
+// taps of one workgroup's tiles stay close in its XCD's L2.
+#include "kernels_common.hpp"
+
+namespace ridg {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kMfmaWaves = 4;
+
+template <int R, int C>
+__global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, const double* __restrict__ in,
+                                                                   const double* __restrict__ base,
+                                                                   double* __restrict__ out,
+                                                                   const double* __restrict__ frag, TapsN taps,
+                                                                   int ntaps, int64_t tiles_per_group) {
+  constexpr int MT = (R + 15) / 16;  // 16-row tiles of the operator
+  constexpr int CQ = (C + 3) / 4;    // K chunks per tap
+  extern __shared__ double s_frag[];  // [MT][ntaps][CQ][64]
+  const int nfrag = MT * ntaps * CQ * 64;
+  for (int i = threadIdx.x; i < nfrag; i += blockDim.x) s_frag[i] = frag[i];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int kq = lane >> 4;  // K index within a chunk (B) / row group (D)
+  const int col = lane & 15;
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t ntiles = (nel + 15) / 16;
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_group;
+  const int64_t t_end = t_begin + tiles_per_group < ntiles ? t_begin + tiles_per_group : ntiles;
+  for (int64_t tile = t_begin + wave; tile < t_end; tile += kMfmaWaves) {
+    const int64_t e = tile * 16 + col;
+    const bool valid = e < nel;
+    int idx[3];
+    elem_idx(g, valid ? e : nel - 1, idx);
+    v4d acc[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int t = 0; t < ntaps; ++t) {
+      const int64_t ne = (int64_t)wrap(idx[0] + taps.off[t][0], g.n0) +
+                         (int64_t)g.n0 * ((int64_t)wrap(idx[1] + taps.off[t][1], g.n1) +
+                                          (int64_t)g.n1 * wrap(idx[2] + taps.off[t][2], g.n2));
+      const double* ft = s_frag + (size_t)t * CQ * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < CQ; ++q) {
+        const int c = 4 * q + kq;
+        // columns past C meet zero rows of A; the load index is clamped to stay inside `in`
+        const double v = in[(int64_t)(c < C ? c : C - 1) * nel + ne];
+        const double b = c < C ? v : 0.0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ft[((size_t)mt * ntaps * CQ + q) * 64], b, acc[mt], 0, 0, 0);
+      }
+    }
+    if (valid) {
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * mt + 4 * r + kq;
+          if (row < R) {
+            const int64_t o = (int64_t)row * nel + e;
+            out[o] = base ? base[o] + acc[mt][r] : acc[mt][r];
+          }
+        }
+    }
+  }
+}
+
+template <int R, int C>
+static int launch_rc(const DevGeom& g, const double* in, const double* base, double* out, const double* frag,
+                     const int32_t* taps, int ntaps, void* stream) {
+  constexpr int MT = (R + 15) / 16, CQ = (C + 3) / 4;
+  if (ntaps <= 0 || ntaps > kMaxTapUpdate) return (int)hipErrorInvalidValue;
+  const size_t lds = (size_t)MT * ntaps * CQ * 64 * 8;
+  if (lds > kMfmaMaxLds) return (int)hipErrorInvalidValue;
+  static const bool attr = hipFuncSetAttribute((const void*)tap_mfma_kernel<R, C>,
+                                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               (int)kMfmaMaxLds) == hipSuccess;
+  if (!attr && lds > 64 * 1024) return (int)hipErrorInvalidValue;
+  TapsN tp;
+  for (int t = 0; t < kMaxTapUpdate; ++t)
+    for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t ntiles = (nel + 15) / 16;
+  // enough workgroups to fill the chip several times over; each sweeps a contiguous tile range
+  const int64_t groups_max = 256 * 8;
+  int64_t groups = (ntiles + kMfmaWaves - 1) / kMfmaWaves;
+  if (groups > groups_max) groups = groups_max;
+  const int64_t per = (ntiles + groups - 1) / groups;
+  groups = (ntiles + per - 1) / per;
+  hipLaunchKernelGGL((tap_mfma_kernel<R, C>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), lds,
+                     (hipStream_t)stream, g, in, base, out, frag, tp, ntaps, per);
+  return (int)hipGetLastError();
+}
+
+template <int D, int M>
+struct MfmaL {
+  static int run(int kind, const DevGeom& g, const double* in, const double* base, double* out, const double* frag,
+                 const int32_t* taps, int ntaps, void* stream) {
+    constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
+    if (kind == kMfmaPredict) return launch_rc<NT, NS>(g, in, base, out, frag, taps, ntaps, stream);
+    if (kind == kMfmaCorrect) return launch_rc<NS, NT>(g, in, base, out, frag, taps, ntaps, stream);
+    return launch_rc<NS, NS>(g, in, base, out, frag, taps, ntaps, stream);
+  }
+};
+
+int launch_tap_mfma(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
+                    const double* frag, const int32_t* taps, int ntaps, void* stream) {
+  return dispatch_dm<MfmaL>(d, M, kind, g, in, base, out, frag, taps, ntaps, stream);
+}
+
+}  // namespace ridg

@@ -145,6 +145,12 @@ void build_correction_taps(const Problem& P, const RefTensors& T, double dt, Tap
 // Prediction and correction composed: Q'_e = Q_e + sum_o K_o Q_{e+o}, K_o = sum_{t+s=o} D_t G_s.
 void build_composite(const Problem& P, const Prefactored& G, const TapOperator& Dc, TapOperator* out);
 constexpr int kMaxTapUpdate = 125;  // composite offsets in {-2..2}^3
+// A operator [tap][rows][cols] rearranged as MFMA A fragments: [row tile][tap][chunk][lane] holding
+// A_t[16 tile + lane % 16][4 chunk + lane / 16], zero outside rows x cols (16x16x4 layout).
+std::vector<double> mfma_fragments(const double* A, int ntaps, int rows, int cols);
+inline size_t mfma_fragment_doubles(int ntaps, int rows, int cols) {
+  return (size_t)((rows + 15) / 16) * ntaps * ((cols + 3) / 4) * 64;
+}
 
 // ---------------------------------------------------------------- device side
 struct DevTensors {  // device copies (FP64), offsets into one buffer
@@ -221,6 +227,11 @@ int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, 
 // kind 0: correction taps (W -> Q' = Q + ...), kind 1: composite taps (Q -> Q' = Q + ...)
 int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                       const double* A, const int32_t* taps, int ntaps, void* stream);
+// The same tap operators on FP64 MFMA; frag = mfma_fragments(...) of the operator (device copy).
+constexpr int kMfmaPredict = 0, kMfmaCorrect = 1, kMfmaComposite = 2;
+constexpr size_t kMfmaMaxLds = 160 * 1024;  // fragments are staged in LDS
+int launch_tap_mfma(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
+                    const double* frag, const int32_t* taps, int ntaps, void* stream);
 // layout: 0 = packed theta_T-lane segments, 1 = power-of-two segments (DPP reductions)
 int launch_predict_plans(int d, int M, int layout, int precision, int refine, const DevGeom& g, double dt,
                          const double* Q, double* W, const PlanTables& t, const PlanRec* plans,

@@ -28,7 +28,7 @@ FLUX_CONST, FLUX_ROTATION, FLUX_AFFINE = 0, 1, 2
 FP64, FP32_REFINE = 0, 1
 SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
-OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE = 1, 2, 3, 4
+OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE, OPT_MFMA = 1, 2, 3, 4, 5
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",

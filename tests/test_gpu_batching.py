@@ -127,6 +127,29 @@ def test_composite_and_tap_correction_match_oracle(d, n, M, v):
     q0 = I.random_state(d, n, M, seed=8)
     dt = 0.45 * min(1.0 / k for k in n) / max(abs(x) for x in v)
     ref = S.step(S.Problem(d=d, n=n, M=M, velocity=("const", v)), q0, dt, 3)
-    for opts in ([], [(ridg.OPT_COMPOSITE, 1)]):
+    for opts in ([], [(ridg.OPT_COMPOSITE, 1)], [(ridg.OPT_MFMA, 1)], [(ridg.OPT_MFMA, 1), (ridg.OPT_COMPOSITE, 1)]):
+        print(f"[gpu] taps d={d} n={n} M={M} {opts}", flush=True)
         got = _run(p, q0, dt, 3, options=opts)
         assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-12, opts
+
+
+@pytest.mark.parametrize("d,n,M,v", [(3, (16, 9, 5), 3, (1.0, -0.7, 0.4)), (2, (33, 17), 4, (-1.0, 0.5)),
+                                     (2, (40, 40), 5, (0.3, 0.9)), (1, (50,), 4, (0.8,)), (3, (5, 4, 6), 4, (0.2, 0.3, -0.9))])
+def test_mfma_tap_kernels_match_vector_kernels(d, n, M, v):
+    """FP64 MFMA tap kernels (prediction, correction, composite) against the vector kernels: ragged
+    tile tails (element counts not multiples of 16), several row tiles (theta_T > 16)."""
+    p = ridg.make_problem(d, n, M, velocity=v)
+    q0 = I.random_state(d, n, M, seed=11)
+    dt = 0.4 * min(1.0 / k for k in n) / max(abs(x) for x in v)
+    print(f"[gpu] mfma d={d} n={n} M={M}", flush=True)
+    for comp in (0, 1):
+        ref = _run(p, q0, dt, 4, options=[(ridg.OPT_COMPOSITE, comp)])
+        got = _run(p, q0, dt, 4, options=[(ridg.OPT_COMPOSITE, comp), (ridg.OPT_MFMA, 1)])
+        assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-13, comp
+
+
+def test_mfma_option_needs_prefactored():
+    sim = ridg.Simulation(_rot(16, 3))
+    with pytest.raises(ridg.RidgError):
+        sim.set_option(ridg.OPT_MFMA, 1)
+    sim.close()
