@@ -28,6 +28,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (same as the vector peak on this part)
 FP32_VECTOR_PEAK_TFLOPS = 157.3  # published FP32 vector peak (counts packed FP32, which this build does not use)
 HBM_PEAK_GBS = 8000.0
 METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error; p99 latency"
@@ -39,7 +40,8 @@ KERNEL_UNITS = {"predict_plans2_kernel": "k_plans.hip", "predict_plans_2r_kernel
                 "predict_prefactored_kernel": "k_prefactored.hip", "tap_update_kernel": "k_prefactored.hip",
                 "fused_prefactored_kernel": "k_prefactored.hip", "correct_kernel": "k_correct.hip",
                 "predict_tear_kernel": "k_tear_dense.hip", "predict_dense_kernel": "k_tear_dense.hip",
-                "batch_predict_kernel": "k_batch.hip", "batch_correct_kernel": "k_batch.hip"}
+                "batch_predict_kernel": "k_batch.hip", "batch_correct_kernel": "k_batch.hip",
+                "tap_mfma_kernel": "k_mfma.hip"}
 RECORD_TAG = "traffic-record: "
 
 
@@ -60,6 +62,10 @@ def dominant_kernel(info, opts, precision):
     from paper_2101_01231_amd import ridg
     d, M = _dim_order(info)
     if info.solver == ridg.SOLVER_PREFACTORED:
+        if opts.get("mfma"):
+            cols = info.theta
+            rows = info.theta if opts.get("composite") else info.theta_t
+            return f"ridg::tap_mfma_kernel<{rows}, {cols}>"
         if opts.get("composite"):
             return f"ridg::tap_update_kernel<{d}, {info.theta}, {info.theta}>"
         return f"ridg::predict_prefactored_kernel<{d}, {M}>"
@@ -221,7 +227,7 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
     sim.set_option(ridg.OPT_GRAPH, 0)
     opts = {"plan_layout": sim.get_option(ridg.OPT_PLAN_LAYOUT), "composite": sim.get_option(ridg.OPT_COMPOSITE),
-            "fused": sim.get_option(ridg.OPT_FUSED)}
+            "fused": sim.get_option(ridg.OPT_FUSED), "mfma": sim.get_option(ridg.OPT_MFMA)}
     if opts["fused"]:
         sim.set_option(ridg.OPT_FUSED, 0)  # one launch for all steps would hide the per-step latency
         opts["fused"] = 0
@@ -373,8 +379,15 @@ def main():
         bw = nbytes / (R["pred_ms"] * 1e-3) / 1e9
         tf = nflops / (R["pred_ms"] * 1e-3) / 1e12
         kern = "composite prediction+correction stencil" if comp else "prediction (prefactored G)"
+        mfma = bool(R["opts"].get("mfma"))
+        if mfma:
+            kern += " on FP64 MFMA"
         # the roof that binds: whichever fraction is larger
-        if bw / HBM_PEAK_GBS >= tf / FP64_VECTOR_PEAK_TFLOPS:
+        if mfma and tf / FP64_MFMA_PEAK_TFLOPS > bw / HBM_PEAK_GBS:
+            roofline.update({"bound": "mfma", "kernel": kern, "achieved": tf, "peak": FP64_MFMA_PEAK_TFLOPS,
+                             "unit": "TFLOP/s", "frac": tf / FP64_MFMA_PEAK_TFLOPS, "flops_per_launch": nflops,
+                             "bytes_per_launch": nbytes, "gbs": bw})
+        elif bw / HBM_PEAK_GBS >= tf / FP64_VECTOR_PEAK_TFLOPS:
             roofline.update({"bound": "hbm", "kernel": kern, "achieved": bw, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": bw / HBM_PEAK_GBS, "bytes_per_launch": nbytes, "flops_per_launch": nflops,
                              "tflops": tf})
