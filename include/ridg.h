@@ -168,8 +168,8 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
  *   RIDG_OPT_PLAN_LAYOUT (REGION): 0 = theta_T-lane segments packed in the wavefront, 1 = segments
  *     padded to a power of two (DPP reductions), 2 = two regions per packed segment with their
  *     eliminations interleaved, 3 = two rows per lane (half-width segments; each published pivot
- *     row is read once for two rows). 2 and 3 are RIDG_FP64 only. Every layout gives bitwise the
- *     same results.
+ *     row is read once for two rows), 4 = up to three rows per lane in power-of-two segments
+ *     (DPP pivot reductions). 2 to 4 are RIDG_FP64 only. Every layout gives bitwise the same results.
  *   RIDG_OPT_FUSED (PREFACTORED, meshes whose state and predictions fit in 160 KB of LDS): run all
  *     n_steps of a ridg_step call in one single-workgroup kernel. */
 #define RIDG_OPT_GRAPH 1

@@ -904,7 +904,7 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
     case RIDG_OPT_PLAN_LAYOUT:
       if (h->P.solver != RIDG_SOLVER_REGION && value) return fail(RIDG_E_UNSUPPORTED, "plan layout applies to REGION");
       if (value >= 2 && h->P.precision != RIDG_FP64)
-        return fail(RIDG_E_UNSUPPORTED, "plan layouts 2 and 3 are FP64 only");
+        return fail(RIDG_E_UNSUPPORTED, "plan layouts 2 to 4 are FP64 only");
       h->opt_layout = (int)value;
       break;
     case RIDG_OPT_FUSED:

@@ -213,19 +213,17 @@ __global__ __launch_bounds__(256) void predict_plans2_kernel(DevGeom g, double d
   if (write[1]) W[(int64_t)k * nel + e[1]] = sw1[(nb - 1) * NT + k];
 }
 
-// Two rows per lane (PlanCfg2R): twice the regions per wavefront of the packed layout, each pivot
-// row read once for two rows. FP64; bitwise the results of the packed layout. Table rows are
-// addressed by 32-bit byte offsets and loaded kLoadChunk at a time (scheduling barriers), which
-// keeps the loads in flight, and with them the register count, bounded.
-template <int D, int M>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D, M>::MIN_WAVES))) void predict_plans_2r_kernel(DevGeom g, double dt, const double* __restrict__ Q,
-                                                               double* __restrict__ W, PlanTables t,
-                                                               const PlanRec* __restrict__ plans,
-                                                               const int32_t* __restrict__ items,
-                                                               const int32_t* __restrict__ item_plan,
-                                                               int64_t n_items) {
-  using C = PlanCfg2R<D, M>;
-  constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB, SEGW = C::SEGW;
+// Several rows per lane (PlanCfgNR): RPL rows of a region's block system in each lane of a
+// SEGW-lane segment, each pivot row read once for RPL rows. FP64; bitwise the results of the
+// packed layout. Table rows are addressed by 32-bit byte offsets and loaded kLoadChunk at a time
+// (scheduling barriers), which keeps the loads in flight, and with them the registers, bounded.
+template <int D, int M, int RPL, int SEGW>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfgNR<D, M, RPL, SEGW>::MIN_WAVES))) void
+predict_plans_nr_kernel(DevGeom g, double dt, const double* __restrict__ Q, double* __restrict__ W, PlanTables t,
+                        const PlanRec* __restrict__ plans, const int32_t* __restrict__ items,
+                        const int32_t* __restrict__ item_plan, int64_t n_items) {
+  using C = PlanCfgNR<D, M, RPL, SEGW>;
+  constexpr int NT = C::NT, S = C::S, NB = C::NB, LB = C::LB;
   __shared__ double s_w[C::WAVES][S][NB][NT];
   __shared__ double s_piv[C::WAVES][S][2 * (NT + 2)];
   const int lane = threadIdx.x & 63;
@@ -233,7 +231,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D
   const bool tail = lane >= S * SEGW;
   const int seg = tail ? 0 : lane / SEGW;
   const int k = tail ? lane - S * SEGW : lane % SEGW;
-  const bool idle[2] = {tail, tail || k + SEGW >= NT};
+  bool idle[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) idle[u] = tail || k + u * SEGW >= NT;
   const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S;
   if (wave_first >= n_items) return;  // the list is padded to S
   int addr[LB > 0 ? LB : 1];
@@ -250,16 +250,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D
   const int nb = pr->nb;
   double* sw = &s_w[wave][seg][0][0];
   double* spiv = &s_piv[wave][seg][0];
-  int kr[2];
-  unsigned rb[2];  // byte offset of row kr within a theta_T x theta_T table
-  int ccl[2];
-  double ccv[2];
+  unsigned rb[RPL];  // byte offset of the lane's rows within a theta_T x theta_T table
+  int ccl[RPL];
+  double ccv[RPL];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    kr[u] = idle[u] ? 0 : k + u * SEGW;
-    rb[u] = (unsigned)kr[u] * (unsigned)(NT * 8);
-    ccl[u] = t.cc_idx[kr[u]];
-    ccv[u] = t.cc_val[kr[u]];
+  for (int u = 0; u < RPL; ++u) {
+    const int kr = idle[u] ? 0 : k + u * SEGW;
+    rb[u] = (unsigned)kr * (unsigned)(NT * 8);
+    ccl[u] = t.cc_idx[kr];
+    ccv[u] = t.cc_val[kr];
   }
   for (int b = 0; b < nb; ++b) {
     const PlanBlock blk = pr->blk[b];
@@ -278,11 +277,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D
       for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
       V0[i] = v * dt / geom_h(g, i);
     }
-    double a[2][NT];
+    double a[RPL][NT];
     {
       const char* a0 = (const char*)t.A0 + (unsigned)mask * (unsigned)(NT * NT * 8);
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < RPL; ++u)
 #pragma unroll
         for (int l = 0; l < NT; ++l) a[u][l] = *(const double*)(a0 + (rb[u] + (unsigned)(l * 8)));
     }
@@ -291,14 +290,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D
       const double vi = sel<D>(V0, i);
       const char* kk = (const char*)t.K + (unsigned)(i * 4 + ((mask >> (2 * i)) & 3)) * (unsigned)(NT * NT * 8);
 #pragma unroll
-      for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < RPL; ++u)
 #pragma unroll
         for (int l = 0; l < NT; ++l) {
           a[u][l] = fma(vi, *(const double*)(kk + (rb[u] + (unsigned)(l * 8))), a[u][l]);
           if (l % kLoadChunk == kLoadChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
     }
-    double rhs[2] = {ccv[0] * Q[(int64_t)ccl[0] * nel + ge], ccv[1] * Q[(int64_t)ccl[1] * nel + ge]};
+    double rhs[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) rhs[u] = ccv[u] * Q[(int64_t)ccl[u] * nel + ge];
 #pragma unroll 1
     for (int i = 0; i < D; ++i) {
       const double vi = sel<D>(V0, i);
@@ -310,25 +311,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg2R<D
         const char* f0 = (const char*)t.Fn0 + toff;
         const char* fc = (const char*)t.FnC + toff;
         const double* wsrc = sw + src * NT;
-        double acc0 = 0.0, acc1 = 0.0;
+        double acc[RPL];
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) acc[u] = 0.0;
 #pragma unroll
         for (int l = 0; l < NT; ++l) {
           const double w = wsrc[l];
-          const unsigned o0 = rb[0] + (unsigned)(l * 8), o1 = rb[1] + (unsigned)(l * 8);
-          acc0 = fma(fma(vi, *(const double*)(f0 + o0), *(const double*)(fc + o0)), w, acc0);
-          acc1 = fma(fma(vi, *(const double*)(f0 + o1), *(const double*)(fc + o1)), w, acc1);
+#pragma unroll
+          for (int u = 0; u < RPL; ++u) {
+            const unsigned o = rb[u] + (unsigned)(l * 8);
+            acc[u] = fma(fma(vi, *(const double*)(f0 + o), *(const double*)(fc + o)), w, acc[u]);
+          }
           if (l % kLoadChunk == kLoadChunk - 1) __builtin_amdgcn_sched_barrier(0);
         }
-        rhs[0] -= acc0;
-        rhs[1] -= acc1;
+#pragma unroll
+        for (int u = 0; u < RPL; ++u) rhs[u] -= acc[u];
       }
     }
-    seg_solve_2r<NT, LB, SEGW>(a, rhs, k, idle, addr, spiv, sw + b * NT);
+    seg_solve_nr<C>(a, rhs, k, idle, addr, spiv, sw + b * NT);
   }
   if (write) {
-    W[(int64_t)k * nel + e] = sw[(nb - 1) * NT + k];
-    if (!idle[1]) W[(int64_t)(k + SEGW) * nel + e] = sw[(nb - 1) * NT + k + SEGW];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u)
+      if (!idle[u]) W[(int64_t)(k + u * SEGW) * nel + e] = sw[(nb - 1) * NT + k + u * SEGW];
   }
+}
+
+template <class C, int D, int M>
+static int launch_nr(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                     const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
+                     void* stream) {
+  const int64_t per_block = (int64_t)C::WAVES * C::S;
+  const int64_t blocks = (n_items + per_block - 1) / per_block;
+  if (blocks == 0) return 0;
+  hipLaunchKernelGGL((predict_plans_nr_kernel<D, M, C::RPL, C::SEGW>), dim3((unsigned)blocks), dim3(64 * C::WAVES),
+                     0, (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
+  return (int)hipGetLastError();
 }
 
 template <int D, int M>
@@ -336,6 +354,7 @@ struct IpwL {
   static int run(int layout) {
     if (layout == 2) return 2 * PlanCfg<D, M, false>::S;
     if (layout == 3) return PlanCfg2R<D, M>::S;
+    if (layout == 4) return PlanCfgDpp<D, M>::S;
     return layout ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S;
   }
 };
@@ -364,15 +383,10 @@ struct PlansL {
                  const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
-    if (layout == 3) {
+    if (layout == 3 || layout == 4) {
       if (precision != RIDG_FP64) return (int)hipErrorInvalidValue;
-      using C = PlanCfg2R<D, M>;
-      const int64_t per_block = (int64_t)C::WAVES * C::S;
-      const int64_t blocks = (n_items + per_block - 1) / per_block;
-      if (blocks == 0) return 0;
-      hipLaunchKernelGGL((predict_plans_2r_kernel<D, M>), dim3((unsigned)blocks), dim3(64 * C::WAVES), 0,
-                         (hipStream_t)stream, g, dt, Q, W, t, plans, items, item_plan, n_items);
-      return (int)hipGetLastError();
+      if (layout == 3) return launch_nr<PlanCfg2R<D, M>, D, M>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
+      return launch_nr<PlanCfgDpp<D, M>, D, M>(g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
     }
     if (layout == 2) {
       if (precision != RIDG_FP64) return (int)hipErrorInvalidValue;

@@ -249,76 +249,105 @@ __device__ inline void seg_solve(double (&a)[NT], double& rhs, int k, bool idle,
   wave_sync();
 }
 
-// Segment geometry with two rows per lane: rows k and k + SEGW of a theta_T-row system live in lane
-// k of a SEGW = ceil(theta_T / 2)-lane segment. Row numbers, hence pivot keys, are those of the
-// one-row layout, so both eliminate in the same order with the same arithmetic.
-template <int D, int M>
-struct PlanCfg2R {
+__host__ __device__ constexpr int log2_ceil(int n) {
+  return n <= 1 ? 0 : n <= 2 ? 1 : n <= 4 ? 2 : n <= 8 ? 3 : n <= 16 ? 4 : n <= 32 ? 5 : 6;
+}
+
+// Several rows per lane: rows k + SEGW u (u = 0 .. RPL-1) of a theta_T-row block system live in lane k
+// of a SEGW-lane segment (rows >= theta_T are idle). Row numbers, hence pivot keys (whose low bits
+// hold the row with the one-row layout's width), are those of the one-row layout, so every layout
+// eliminates in the same order with the same arithmetic. Power-of-two segments of at most 16
+// lanes reduce the pivot key with DPP row operations, other widths with ds_bpermute rotations.
+template <int D, int M, int RPL_, int SEGW_>
+struct PlanCfgNR {
   static constexpr int NS = n_space(D, M);
   static constexpr int NT = n_spacetime(D, M);
-  static constexpr int SEGW = (NT + 1) / 2;
+  static constexpr int RPL = RPL_;
+  static constexpr int SEGW = SEGW_;
+  static_assert(RPL * SEGW >= NT, "segment too small");
   static constexpr int S = 64 / SEGW;
-  static constexpr int LB = SEGW <= 1 ? 0 : SEGW <= 2 ? 1 : SEGW <= 4 ? 2 : SEGW <= 8 ? 3 : SEGW <= 16 ? 4 : SEGW <= 32 ? 5 : 6;
+  static constexpr bool POW2 = (SEGW & (SEGW - 1)) == 0 && SEGW <= 16;
+  static constexpr int LB = log2_ceil(SEGW);   // rotation rounds (non-power-of-two segments)
+  static constexpr int LBK = log2_ceil(NT);    // row bits of the pivot key
   static constexpr int NB = D == 3 ? 8 : pow3(D);
   static constexpr int WAVES = 4;
-  // register budget hint: 2D order 4 at three waves per SIMD (168 VGPRs, a few spilled) beats two
-  static constexpr int MIN_WAVES = (D == 2 && M == 4) ? 3 : 1;
+  // register budget hint: two rows per lane at 2D order 4 run best at three waves per SIMD
+  // (168 VGPRs, a few spilled); elsewhere the compiler's own choice is kept
+  static constexpr int MIN_WAVES = (RPL == 2 && D == 2 && M == 4) ? 3 : 1;
 };
+// layout 3: two rows per lane, ceil(theta_T / 2)-lane segments
+template <int D, int M>
+using PlanCfg2R = PlanCfgNR<D, M, 2, (n_spacetime(D, M) + 1) / 2>;
+// layout 4: power-of-two segments of SEGW >= theta_T / 3 lanes, ceil(theta_T / SEGW) rows per lane
+__host__ __device__ constexpr int seg_width_nr(int nt) { return seg_width((nt + 2) / 3); }
+template <int D, int M>
+using PlanCfgDpp = PlanCfgNR<D, M, (n_spacetime(D, M) + seg_width_nr(n_spacetime(D, M)) - 1) / seg_width_nr(n_spacetime(D, M)),
+                             seg_width_nr(n_spacetime(D, M))>;
 
-// Gauss-Jordan with partial pivoting as seg_solve, each lane holding two rows: one read of the
-// published pivot row updates both (half the LDS traffic of one row per lane).
-template <int NT, int LB, int SEGW>
-__device__ inline void seg_solve_2r(double (&a)[2][NT], double (&rhs)[2], int k, const bool (&idle)[2],
-                                    const int (&addr)[LB > 0 ? LB : 1], double* piv, double* x) {
-  constexpr unsigned LMASK = (2u << LB) - 1u;  // row numbers 0 .. 2 SEGW - 1
+// Gauss-Jordan with partial pivoting as seg_solve, each lane holding RPL rows: one read of the
+// published pivot row updates all of them (1/RPL of the LDS traffic of one row per lane).
+template <class C>
+__device__ inline void seg_solve_nr(double (&a)[C::RPL][C::NT], double (&rhs)[C::RPL], int k,
+                                    const bool (&idle)[C::RPL], const int (&addr)[C::LB > 0 ? C::LB : 1], double* piv,
+                                    double* x) {
+  constexpr int NT = C::NT, RPL = C::RPL, SEGW = C::SEGW;
+  constexpr unsigned LMASK = (1u << C::LBK) - 1u;
   constexpr int PS = NT + 2;
   static_assert(2 * PS <= 256, "ds_write2_b64 offsets are 8-bit");
-  bool used[2] = {idle[0], idle[1]};
-  int step[2] = {-1, -1};
-  double inv[2] = {0.0, 0.0};
+  bool used[RPL];
+  int step[RPL];
+  double inv[RPL];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u) {
+    used[u] = idle[u];
+    step[u] = -1;
+    inv[u] = 0.0;
+  }
   const unsigned pbase = lds_addr(piv);
-  static_for<0, NT>([&](auto C) {
-    constexpr int c = decltype(C)::value;
+  static_for<0, NT>([&](auto CC) {
+    constexpr int c = decltype(CC)::value;
     constexpr int off = (c & 1) * PS;
     const double* pv = piv + off;
     unsigned key = 0u;
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < RPL; ++u)
       if (!used[u])
         key = max(key, (__float_as_uint((float)fabs(a[u][c])) & ~LMASK) | (LMASK - (unsigned)(k + u * SEGW)));
-    key = seg_max_rot<SEGW, LB>(key, addr);
+    if constexpr (C::POW2)
+      key = seg_max_pow2<SEGW>(key);
+    else
+      key = seg_max_rot<SEGW, C::LB>(key, addr);
     const int p = (int)(LMASK - (key & LMASK));
-    const bool piv0 = (p == k) && !idle[0];
-    const bool piv1 = (p == k + SEGW) && !idle[1];
-    if (piv0) {
-      inv[0] = recip(a[0][c]);
-      publish_row<off, c + 1, NT>(pbase, a[0], rhs[0], inv[0]);
-      used[0] = true;
-      step[0] = c;
-    }
-    if (piv1) {
-      inv[1] = recip(a[1][c]);
-      publish_row<off, c + 1, NT>(pbase, a[1], rhs[1], inv[1]);
-      used[1] = true;
-      step[1] = c;
+    bool pivu[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+      pivu[u] = (p == k + u * SEGW) && !idle[u];
+      if (pivu[u]) {
+        inv[u] = recip(a[u][c]);
+        publish_row<off, c + 1, NT>(pbase, a[u], rhs[u], inv[u]);
+        used[u] = true;
+        step[u] = c;
+      }
     }
     wave_sync();
     // every row but the pivot row (and idle rows) is reduced; a zero multiplier leaves a row as is
     const double ip = pv[NT + 1];
-    const double l0 = (piv0 || idle[0]) ? 0.0 : a[0][c] * ip;
-    const double l1 = (piv1 || idle[1]) ? 0.0 : a[1][c] * ip;
+    double l[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) l[u] = (pivu[u] || idle[u]) ? 0.0 : a[u][c] * ip;
 #pragma unroll
     for (int j = c + 1; j < NT; ++j) {
       const double v = pv[j];
-      a[0][j] = fma(-l0, v, a[0][j]);
-      a[1][j] = fma(-l1, v, a[1][j]);
+#pragma unroll
+      for (int u = 0; u < RPL; ++u) a[u][j] = fma(-l[u], v, a[u][j]);
     }
     const double pr = pv[NT];
-    rhs[0] = fma(-l0, pr, rhs[0]);
-    rhs[1] = fma(-l1, pr, rhs[1]);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) rhs[u] = fma(-l[u], pr, rhs[u]);
   });
-  if (step[0] >= 0) x[step[0]] = rhs[0] * inv[0];
-  if (step[1] >= 0) x[step[1]] = rhs[1] * inv[1];
+#pragma unroll
+  for (int u = 0; u < RPL; ++u)
+    if (step[u] >= 0) x[step[u]] = rhs[u] * inv[u];
   wave_sync();
 }
 

@@ -59,7 +59,7 @@ def test_plan_layouts_agree(case):
         ref_prob = S.Problem(d=1, n=(29,), M=5, velocity=("const", (-0.7,)))
     print(f"[gpu] plan layouts {case}", flush=True)
     a = _run(p, q0, dt, 3)
-    for lay in (1, 2, 3):
+    for lay in (1, 2, 3, 4):
         b = _run(p, q0, dt, 3, options=[(ridg.OPT_PLAN_LAYOUT, lay)])
         assert np.array_equal(a, b), lay
     ref = S.step(ref_prob, q0, dt, 3)
@@ -74,6 +74,8 @@ def test_two_region_layout_rejected_for_fp32():
         sim.set_option(ridg.OPT_PLAN_LAYOUT, 2)
     with pytest.raises(ridg.RidgError):
         sim.set_option(ridg.OPT_PLAN_LAYOUT, 3)
+    with pytest.raises(ridg.RidgError):
+        sim.set_option(ridg.OPT_PLAN_LAYOUT, 5)
     sim.close()
 
 
