@@ -507,6 +507,26 @@ static int dispatch_dm(int d, int M, Args... args) {
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // ---------------------------------------------------------------- correction (per element)
+// acc -= sum_p V_ip tens[i][sd][p] w (the face term of direction i, side sd)
+template <int D, int M, bool AFFINE>
+__device__ inline void face_term(const double* tens, int i, int sd, const double (&V)[D][D + 1],
+                                 const double (&w)[n_spacetime(D, M)], double (&acc)[n_space(D, M)]) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NP = D + 1;
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    if (p == 1 + i || (!AFFINE && p > 0)) continue;
+    const double vp = V[i][p];
+    const double* cf = tens + (((size_t)i * 2 + sd) * NP + p) * NS * NT;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double s2 = 0.0;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) s2 = fma(cf[k * NT + l], w[l], s2);
+      acc[k] = fma(-vp, s2, acc[k]);
+    }
+  }
+}
+
 // Q'_e = Q_e + 2^-d [ sum_i sum_p V_ip Cv_ip W_e - sum_faces sum_p V_ip (CFo W_e | CFn W_nbr) ]
 template <int D, int M, bool AFFINE>
 __device__ inline void correct_elem(const DevGeom& g, double dt, const double* Q, const double* W, double* Qout,
@@ -540,32 +560,18 @@ __device__ inline void correct_elem(const DevGeom& g, double dt, const double* Q
     for (int sd = 0; sd < 2; ++sd) {
       const int s = sd ? 1 : -1;
       const int side = face_side<D>(g, idx, i, s);
-      double wn[NT];
-      const double* tens;
+      // two branches with wave-uniform tensor pointers (scalar loads); a wavefront whose elements
+      // disagree on the face's upwind side runs both, each on its own lanes
       if (side == 0) {
-#pragma unroll
-        for (int l = 0; l < NT; ++l) wn[l] = we[l];
-        tens = t.CFo;
+        face_term<D, M, AFFINE>(t.CFo, i, sd, V, we, acc);
       } else {
         int j[3] = {idx[0], idx[1], idx[2]};
         j[i] += s;
         const int64_t en = elem_lin(g, j[0], j[1], j[2]);
+        double wn[NT];
 #pragma unroll
         for (int l = 0; l < NT; ++l) wn[l] = W[(int64_t)l * nel + en];
-        tens = t.CFn;
-      }
-#pragma unroll 1
-      for (int p = 0; p < NP; ++p) {
-        if (p == 1 + i || (!AFFINE && p > 0)) continue;
-        const double vp = V[i][p];
-        const double* cf = tens + (((size_t)i * 2 + sd) * NP + p) * NS * NT;
-#pragma unroll
-        for (int k = 0; k < NS; ++k) {
-          double s2 = 0.0;
-#pragma unroll
-          for (int l = 0; l < NT; ++l) s2 = fma(cf[k * NT + l], wn[l], s2);
-          acc[k] = fma(-vp, s2, acc[k]);
-        }
+        face_term<D, M, AFFINE>(t.CFn, i, sd, V, wn, acc);
       }
     }
   }
