@@ -178,8 +178,7 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
 #define RIDG_OPT_COMPOSITE 4 /* PREFACTORED: prediction and correction composed into one stencil on the
                                 state, K_o = sum D_t G_s (the predictions are not stored) */
 #define RIDG_OPT_MFMA 5      /* PREFACTORED: the prediction, correction or composite stencil as stacked-
-                                right-hand-side products on the FP64 matrix cores (operators whose
-                                fragments exceed 160 KB of LDS stay on the vector kernels) */
+                                right-hand-side products on the FP64 matrix cores */
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value);
 int ridg_get_option(ridg_t* h, int32_t option, int64_t* value);
 

@@ -704,18 +704,14 @@ static int direct_step(ridg_t* h, double dt) {
     if (err) return hip_fail(err, "timing event");
   }
   const int nk = (int)h->host_ktaps.size() / 3, nd = (int)h->host_dtaps.size() / 3;
-  const int ns = h->T.ns, nt = h->T.nt;
-  // MFMA kernels stage the operator's fragments in LDS: operators too large for it stay on the VALU kernels
-  auto fits = [](int ntaps, int rows, int cols) { return mfma_fragment_doubles(ntaps, rows, cols) * 8 <= kMfmaMaxLds; };
-  const bool mfma_k = h->opt_mfma && fits(nk, ns, ns);
-  const bool mfma_pc = h->opt_mfma && fits(h->ntaps, nt, ns) && fits(nd, ns, nt);
+  const bool mfma = h->opt_mfma != 0;
   if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
-    int err = mfma_k ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
+    int err = mfma ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
                                             h->Q[1 - h->cur], h->Fk, h->host_ktaps.data(), nk, h->stream)
                           : launch_tap_update(P.d, P.M, 1, h->geom, h->Q[h->cur], h->Q[h->cur], h->Q[1 - h->cur],
                                               h->Kc, h->host_ktaps.data(), nk, h->stream);
     if (err) return hip_fail(err, "composite launch");
-  } else if (pref && mfma_pc) {
+  } else if (pref && mfma) {
     int err = launch_tap_mfma(P.d, P.M, kMfmaPredict, h->geom, h->Q[h->cur], nullptr, h->W, h->Fg,
                               h->host_taps.data(), h->ntaps, h->stream);
     if (err) return hip_fail(err, "prediction launch");
@@ -728,7 +724,7 @@ static int direct_step(ridg_t* h, double dt) {
     if (err) return hip_fail(err, "timing event");
   }
   int err = 0;
-  if (pref && !h->opt_composite && mfma_pc)
+  if (pref && !h->opt_composite && mfma)
     err = launch_tap_mfma(P.d, P.M, kMfmaCorrect, h->geom, h->W, h->Q[h->cur], h->Q[1 - h->cur], h->Fd,
                           h->host_dtaps.data(), nd, h->stream);
   else if (pref && !h->opt_composite)

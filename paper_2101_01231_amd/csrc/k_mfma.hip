@@ -12,7 +12,8 @@
 // B[l / 16][l % 16] and D[4 r + l / 16][l % 16] in its r-th result register, r = 0..3.
 //
 // The A fragments are precomputed on the host in exactly that order ([row tile][tap][chunk][lane])
-// and staged once per workgroup in LDS; each workgroup then sweeps a contiguous range of tiles,
+// and staged once per workgroup in LDS (read through the caches when they exceed it); each
+// workgroup then sweeps a contiguous range of tiles,
 // so consecutive workgroups (spread over the XCDs) work on distant parts of the mesh while the
 // taps of one workgroup's tiles stay close in its XCD's L2.
 #include "kernels_common.hpp"
@@ -23,7 +24,7 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWaves = 4;
 
-template <int R, int C>
+template <int R, int C, bool LDS_FRAG>
 __global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, const double* __restrict__ in,
                                                                    const double* __restrict__ base,
                                                                    double* __restrict__ out,
@@ -32,9 +33,13 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, co
   constexpr int MT = (R + 15) / 16;  // 16-row tiles of the operator
   constexpr int CQ = (C + 3) / 4;    // K chunks per tap
   extern __shared__ double s_frag[];  // [MT][ntaps][CQ][64]
-  const int nfrag = MT * ntaps * CQ * 64;
-  for (int i = threadIdx.x; i < nfrag; i += blockDim.x) s_frag[i] = frag[i];
-  __syncthreads();
+  const double* fsrc = frag;           // operators too large for LDS are read through the caches
+  if constexpr (LDS_FRAG) {
+    const int nfrag = MT * ntaps * CQ * 64;
+    for (int i = threadIdx.x; i < nfrag; i += blockDim.x) s_frag[i] = frag[i];
+    __syncthreads();
+    fsrc = s_frag;
+  }
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int kq = lane >> 4;  // K index within a chunk (B) / row group (D)
@@ -55,7 +60,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, co
       const int64_t ne = (int64_t)wrap(idx[0] + taps.off[t][0], g.n0) +
                          (int64_t)g.n0 * ((int64_t)wrap(idx[1] + taps.off[t][1], g.n1) +
                                           (int64_t)g.n1 * wrap(idx[2] + taps.off[t][2], g.n2));
-      const double* ft = s_frag + (size_t)t * CQ * 64 + lane;
+      const double* ft = fsrc + (size_t)t * CQ * 64 + lane;
 #pragma unroll
       for (int q = 0; q < CQ; ++q) {
         const int c = 4 * q + kq;
@@ -88,11 +93,10 @@ static int launch_rc(const DevGeom& g, const double* in, const double* base, dou
   constexpr int MT = (R + 15) / 16, CQ = (C + 3) / 4;
   if (ntaps <= 0 || ntaps > kMaxTapUpdate) return (int)hipErrorInvalidValue;
   const size_t lds = (size_t)MT * ntaps * CQ * 64 * 8;
-  if (lds > kMfmaMaxLds) return (int)hipErrorInvalidValue;
-  static const bool attr = hipFuncSetAttribute((const void*)tap_mfma_kernel<R, C>,
+  static const bool attr = hipFuncSetAttribute((const void*)tap_mfma_kernel<R, C, true>,
                                                hipFuncAttributeMaxDynamicSharedMemorySize,
                                                (int)kMfmaMaxLds) == hipSuccess;
-  if (!attr && lds > 64 * 1024) return (int)hipErrorInvalidValue;
+  const bool in_lds = lds <= (attr ? kMfmaMaxLds : (size_t)64 * 1024);
   TapsN tp;
   for (int t = 0; t < kMaxTapUpdate; ++t)
     for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
@@ -104,8 +108,12 @@ static int launch_rc(const DevGeom& g, const double* in, const double* base, dou
   if (groups > groups_max) groups = groups_max;
   const int64_t per = (ntiles + groups - 1) / groups;
   groups = (ntiles + per - 1) / per;
-  hipLaunchKernelGGL((tap_mfma_kernel<R, C>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), lds,
-                     (hipStream_t)stream, g, in, base, out, frag, tp, ntaps, per);
+  if (in_lds)
+    hipLaunchKernelGGL((tap_mfma_kernel<R, C, true>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), lds,
+                       (hipStream_t)stream, g, in, base, out, frag, tp, ntaps, per);
+  else
+    hipLaunchKernelGGL((tap_mfma_kernel<R, C, false>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), 0,
+                       (hipStream_t)stream, g, in, base, out, frag, tp, ntaps, per);
   return (int)hipGetLastError();
 }
 

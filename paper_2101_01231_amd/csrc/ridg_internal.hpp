@@ -229,7 +229,7 @@ int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in
                       const double* A, const int32_t* taps, int ntaps, void* stream);
 // The same tap operators on FP64 MFMA; frag = mfma_fragments(...) of the operator (device copy).
 constexpr int kMfmaPredict = 0, kMfmaCorrect = 1, kMfmaComposite = 2;
-constexpr size_t kMfmaMaxLds = 160 * 1024;  // fragments are staged in LDS
+constexpr size_t kMfmaMaxLds = 160 * 1024;  // fragments up to this size are staged in LDS
 int launch_tap_mfma(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                     const double* frag, const int32_t* taps, int ntaps, void* stream);
 // layout: 0 = packed theta_T-lane segments, 1 = power-of-two segments (DPP reductions)
