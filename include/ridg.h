@@ -190,10 +190,11 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
 
 /* Serving: advance `count` handles by n_steps steps, handle i with step size dts[i], in shared
  * launches queued on hip_stream (the handles' own streams are not used; order calls on them with
- * ridg_synchronize or by using that same stream). Handles with the same dimension and order share
- * one prediction and one correction launch per step (up to 16 per launch). Every handle must use
+ * ridg_synchronize or by using that same stream). Handles with the same dimension, order and
+ * RIDG_OPT_MFMA setting share one prediction and one correction launch per step (up to 16 per
+ * launch; the matrix-core or the vector kernels, as the option selects). Every handle must use
  * RIDG_SOLVER_PREFACTORED (constant velocity) on the same device and appear once; each state
- * advances exactly as ridg_step would advance it alone. */
+ * advances exactly as ridg_step would advance it alone with RIDG_OPT_COMPOSITE off. */
 int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, int32_t n_steps, void* hip_stream);
 
 /* Wait for all queued work of the handle. */

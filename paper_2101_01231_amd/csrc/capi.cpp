@@ -836,12 +836,13 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
     if (rc) return rc;
     if (handles[i]->ntaps > kBatchTaps) return fail(RIDG_E_UNSUPPORTED, "more than 8 taps");
   }
-  // families: same (dim, order)
+  // families: same (dim, order, matrix-core option); a handle steps with the kernels it would use alone
   std::vector<std::vector<int>> fam;
   for (int i = 0; i < count; ++i) {
     bool placed = false;
     for (auto& f : fam)
-      if (handles[f[0]]->P.d == handles[i]->P.d && handles[f[0]]->P.M == handles[i]->P.M) {
+      if (handles[f[0]]->P.d == handles[i]->P.d && handles[f[0]]->P.M == handles[i]->P.M &&
+          (handles[f[0]]->opt_mfma != 0) == (handles[i]->opt_mfma != 0)) {
         f.push_back(i);
         placed = true;
         break;
@@ -851,6 +852,34 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
   for (int s = 0; s < n_steps; ++s) {
     for (auto& f : fam) {
       const ridg_t* h0 = handles[f[0]];
+      if (h0->opt_mfma) {  // prediction, then correction, each one launch per chunk of problems
+        for (size_t c0 = 0; c0 < f.size(); c0 += kBatchMax) {
+          for (int kind : {kMfmaPredict, kMfmaCorrect}) {
+            BatchMfmaArgs args{};
+            int64_t groups = 0;
+            for (size_t c = c0; c < f.size() && c < c0 + kBatchMax; ++c) {
+              ridg_t* h = handles[f[c]];
+              BatchMfmaDesc& d = args.d[args.count++];
+              const bool pred = kind == kMfmaPredict;
+              d.in = pred ? h->Q[h->cur] : h->W;
+              d.base = pred ? nullptr : h->Q[h->cur];
+              d.out = pred ? h->W : h->Q[1 - h->cur];
+              d.frag = pred ? h->Fg : h->Fd;
+              const std::vector<int32_t>& tl = pred ? h->host_taps : h->host_dtaps;
+              d.ntaps = (int32_t)tl.size() / 3;
+              for (int t = 0; t < d.ntaps && t < kBatchTaps; ++t)
+                for (int i = 0; i < 3; ++i) d.taps[t][i] = (int8_t)tl[3 * t + i];
+              for (int i = 0; i < 3; ++i) d.n[i] = h->P.n[i];
+              d.tiles_per_group = mfma_tiles_per_group(h->P.nel);
+              d.group_begin = groups;
+              groups += ((h->P.nel + 15) / 16 + d.tiles_per_group - 1) / d.tiles_per_group;
+            }
+            int err = launch_batch_mfma(h0->P.d, h0->P.M, kind, args, groups, hip_stream);
+            if (err) return hip_fail(err, "batched MFMA launch");
+          }
+        }
+        continue;
+      }
       for (size_t c0 = 0; c0 < f.size(); c0 += kBatchMax) {
         BatchArgs args{};
         int64_t blk = 0;

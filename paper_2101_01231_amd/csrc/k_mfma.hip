@@ -24,31 +24,19 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int kMfmaWaves = 4;
 
-template <int R, int C, bool LDS_FRAG>
-__global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, const double* __restrict__ in,
-                                                                   const double* __restrict__ base,
-                                                                   double* __restrict__ out,
-                                                                   const double* __restrict__ frag, TapsN taps,
-                                                                   int ntaps, int64_t tiles_per_group) {
+// One wavefront: column tiles tile = t_begin + first, t_begin + first + stride, ... < t_end of the
+// product out = base + sum_t A_t in_{e+off_t}; A fragments at fsrc (LDS or global).
+template <int R, int C, class TAPS>
+__device__ inline void mfma_tiles(const DevGeom& g, const double* __restrict__ in, const double* __restrict__ base,
+                                  double* __restrict__ out, const double* fsrc, const TAPS& taps, int ntaps,
+                                  int64_t t_begin, int64_t t_end, int first, int stride) {
   constexpr int MT = (R + 15) / 16;  // 16-row tiles of the operator
   constexpr int CQ = (C + 3) / 4;    // K chunks per tap
-  extern __shared__ double s_frag[];  // [MT][ntaps][CQ][64]
-  const double* fsrc = frag;           // operators too large for LDS are read through the caches
-  if constexpr (LDS_FRAG) {
-    const int nfrag = MT * ntaps * CQ * 64;
-    for (int i = threadIdx.x; i < nfrag; i += blockDim.x) s_frag[i] = frag[i];
-    __syncthreads();
-    fsrc = s_frag;
-  }
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const int kq = lane >> 4;  // K index within a chunk (B) / row group (D)
   const int col = lane & 15;
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int64_t ntiles = (nel + 15) / 16;
-  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_group;
-  const int64_t t_end = t_begin + tiles_per_group < ntiles ? t_begin + tiles_per_group : ntiles;
-  for (int64_t tile = t_begin + wave; tile < t_end; tile += kMfmaWaves) {
+  for (int64_t tile = t_begin + first; tile < t_end; tile += stride) {
     const int64_t e = tile * 16 + col;
     const bool valid = e < nel;
     int idx[3];
@@ -87,6 +75,53 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, co
   }
 }
 
+template <int R, int C, bool LDS_FRAG>
+__global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, const double* __restrict__ in,
+                                                                   const double* __restrict__ base,
+                                                                   double* __restrict__ out,
+                                                                   const double* __restrict__ frag, TapsN taps,
+                                                                   int ntaps, int64_t tiles_per_group) {
+  constexpr int MT = (R + 15) / 16, CQ = (C + 3) / 4;
+  extern __shared__ double s_frag[];  // [MT][ntaps][CQ][64]
+  const double* fsrc = frag;           // operators too large for LDS are read through the caches
+  if constexpr (LDS_FRAG) {
+    const int nfrag = MT * ntaps * CQ * 64;
+    for (int i = threadIdx.x; i < nfrag; i += blockDim.x) s_frag[i] = frag[i];
+    __syncthreads();
+    fsrc = s_frag;
+  }
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t ntiles = (nel + 15) / 16;
+  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_group;
+  const int64_t t_end = t_begin + tiles_per_group < ntiles ? t_begin + tiles_per_group : ntiles;
+  mfma_tiles<R, C>(g, in, base, out, fsrc, taps, ntaps, t_begin, t_end, threadIdx.x >> 6, kMfmaWaves);
+}
+
+// Shared launch for several problems of one (dimension, order) family (serving): a workgroup finds
+// its problem from the group ranges; per element the arithmetic is that of tap_mfma_kernel, so a
+// problem's result does not depend on what it is batched with. Fragments are read through the caches.
+template <int R, int C>
+__global__ __launch_bounds__(64 * kMfmaWaves) void batch_mfma_kernel(BatchMfmaArgs args) {
+  int r = 0;
+  for (int q = 1; q < args.count; ++q)
+    if ((int64_t)blockIdx.x >= args.d[q].group_begin) r = q;
+  const BatchMfmaDesc& bd = args.d[r];
+  DevGeom g{};
+  g.n0 = bd.n[0];
+  g.n1 = bd.n[1];
+  g.n2 = bd.n[2];
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t ntiles = (nel + 15) / 16;
+  const int64_t t_begin = ((int64_t)blockIdx.x - bd.group_begin) * bd.tiles_per_group;
+  const int64_t t_end = t_begin + bd.tiles_per_group < ntiles ? t_begin + bd.tiles_per_group : ntiles;
+  BatchMfmaTaps tp;
+#pragma unroll
+  for (int t = 0; t < kBatchTaps; ++t)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) tp.off[t][i] = bd.taps[t][i];
+  mfma_tiles<R, C>(g, bd.in, bd.base, bd.out, bd.frag, tp, bd.ntaps, t_begin, t_end, threadIdx.x >> 6, kMfmaWaves);
+}
+
 template <int R, int C>
 static int launch_rc(const DevGeom& g, const double* in, const double* base, double* out, const double* frag,
                      const int32_t* taps, int ntaps, void* stream) {
@@ -103,11 +138,8 @@ static int launch_rc(const DevGeom& g, const double* in, const double* base, dou
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   const int64_t ntiles = (nel + 15) / 16;
   // enough workgroups to fill the chip several times over; each sweeps a contiguous tile range
-  const int64_t groups_max = 256 * 8;
-  int64_t groups = (ntiles + kMfmaWaves - 1) / kMfmaWaves;
-  if (groups > groups_max) groups = groups_max;
-  const int64_t per = (ntiles + groups - 1) / groups;
-  groups = (ntiles + per - 1) / per;
+  const int64_t per = mfma_tiles_per_group(nel);
+  const int64_t groups = (ntiles + per - 1) / per;
   if (in_lds)
     hipLaunchKernelGGL((tap_mfma_kernel<R, C, true>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), lds,
                        (hipStream_t)stream, g, in, base, out, frag, tp, ntaps, per);
@@ -131,6 +163,33 @@ struct MfmaL {
 int launch_tap_mfma(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                     const double* frag, const int32_t* taps, int ntaps, void* stream) {
   return dispatch_dm<MfmaL>(d, M, kind, g, in, base, out, frag, taps, ntaps, stream);
+}
+
+int mfma_tiles_per_group(int64_t nel) {
+  const int64_t ntiles = (nel + 15) / 16;
+  int64_t groups = (ntiles + kMfmaWaves - 1) / kMfmaWaves;
+  if (groups > 256 * 8) groups = 256 * 8;
+  return (int)((ntiles + groups - 1) / groups);
+}
+
+template <int D, int M>
+struct BatchMfmaL {
+  static int run(int kind, const BatchMfmaArgs& a, int64_t groups, void* stream) {
+    constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
+    if (a.count <= 0 || groups <= 0) return 0;
+    if (kind == kMfmaPredict)
+      hipLaunchKernelGGL((batch_mfma_kernel<NT, NS>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), 0,
+                         (hipStream_t)stream, a);
+    else
+      hipLaunchKernelGGL((batch_mfma_kernel<NS, NT>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), 0,
+                         (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+  }
+};
+
+int launch_batch_mfma(int d, int M, int kind, const BatchMfmaArgs& args, int64_t groups, void* stream) {
+  if (kind != kMfmaPredict && kind != kMfmaCorrect) return (int)hipErrorInvalidValue;
+  return dispatch_dm<BatchMfmaL>(d, M, kind, args, groups, stream);
 }
 
 }  // namespace ridg

@@ -219,6 +219,30 @@ struct BatchArgs {
 };
 int launch_batch_step(int d, int M, const BatchArgs& args, const DevTensors& t, void* stream);
 
+// Batched MFMA tap products (prediction or correction of several constant-velocity problems of one
+// (dimension, order) family in one launch); workgroups [group_begin, next group_begin) serve a problem.
+struct BatchMfmaDesc {
+  const double* in;
+  const double* base;  // nullptr: out = product
+  double* out;
+  const double* frag;  // MFMA fragments of the operator (mfma_fragments)
+  int64_t group_begin;
+  int64_t tiles_per_group;
+  int32_t n[3];
+  int32_t ntaps;
+  int8_t taps[kBatchTaps][3];
+};
+struct BatchMfmaArgs {
+  BatchMfmaDesc d[kBatchMax];
+  int32_t count;
+  int32_t pad;
+};
+struct BatchMfmaTaps {
+  int8_t off[kBatchTaps][3];
+};
+int mfma_tiles_per_group(int64_t nel);  // the tile range a workgroup sweeps (same split alone and batched)
+int launch_batch_mfma(int d, int M, int kind, const BatchMfmaArgs& args, int64_t groups, void* stream);
+
 // Launchers (defined in the k_*.hip units). All return a hipError_t as int.
 int launch_aos_to_soa(const double* src, double* dst, int64_t nel, int nmodes, void* stream);
 int launch_soa_to_aos(const double* src, double* dst, int64_t nel, int nmodes, void* stream);

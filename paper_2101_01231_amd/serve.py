@@ -8,6 +8,8 @@ order, each with its own number of steps and step size) arrive over time. The se
   * keeps every admitted request's state resident on the device;
   * on each tick advances all active requests by one step with shared launches
     (`ridg_step_batch`: one prediction and one correction launch per (dimension, order) family);
+    requests with large space-time bases (theta_T >= MFMA_MIN_THETA_T) run on the FP64 matrix
+    cores, the others on the vector kernels (the same choice is made when a request runs alone);
   * retires finished requests (state copied back, workspace freed) and admits waiting ones.
 
 Per-step latency is measured with HIP events on the server's stream (a step becomes eligible when
@@ -22,6 +24,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import inputs, ridg
+
+# measured on MI355X: the MFMA tap kernels win from theta_T ~ 30 up (2D order 5, 3D orders 4-5)
+MFMA_MIN_THETA_T = 30
 
 
 @dataclass
@@ -44,6 +49,16 @@ class Request:
         if self.q0 is None:
             self.q0 = inputs.gaussian_bump_state(self.d, self.n, self.M, self.seed)
         return self.q0
+
+    @property
+    def theta_t(self):
+        from math import comb
+        return comb(self.M + self.d, self.d + 1)
+
+    def configure(self, sim):
+        """Kernel choice of the serving policy (applied alone and in the mix alike)."""
+        if self.theta_t >= MFMA_MIN_THETA_T:
+            sim.set_option(ridg.OPT_MFMA, 1)
 
     @property
     def st_dofs_per_step(self):
@@ -75,6 +90,7 @@ class Server:
         if self.used + need > self.budget:
             return None
         sim = ridg.Simulation(prob, device=self.device, stream=self.stream)
+        req.configure(sim)
         sim.set_state(req.initial_state())
         self.used += need
         return dict(req=req, sim=sim, bytes=need, done=0, admitted=time.perf_counter())
@@ -148,6 +164,7 @@ class Server:
 def run_alone(req, device="cuda:0"):
     """The same request advanced on its own handle with ridg_step (reference for the mix)."""
     sim = ridg.Simulation(req.problem(), device=device)
+    req.configure(sim)
     sim.set_state(req.initial_state())
     sim.step(req.steps, req.dt)
     out = sim.get_state()

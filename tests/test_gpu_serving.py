@@ -1,7 +1,8 @@
 """GPU: the serving row - continuous batching of independent runs with shared launches.
 
 Each request's result in the mix must equal (bitwise) the same request advanced alone with
-ridg_step: the batched kernels run the same per-element arithmetic."""
+ridg_step: the batched kernels (vector and matrix-core families) run the same per-element
+arithmetic."""
 
 import numpy as np
 import pytest
@@ -21,6 +22,10 @@ def _mix():
         dict(id=5, arrival=0.05, d=2, n=(20, 64), M=1, steps=20, velocity=(0.2, 0.6), seed=6),
         dict(id=6, arrival=0.08, d=3, n=(8, 8, 8), M=5, steps=15, velocity=(0.5, 0.5, -0.5), seed=7),
         dict(id=7, arrival=0.10, d=2, n=(40, 40), M=2, steps=60, velocity=(0.0, -0.7), seed=8),
+        # theta_T >= 30: the matrix-core family (two 2D order-5 requests share its launches)
+        dict(id=8, arrival=0.00, d=2, n=(30, 28), M=5, steps=20, velocity=(0.6, -0.4), seed=9),
+        dict(id=9, arrival=0.01, d=2, n=(21, 24), M=5, steps=25, velocity=(-0.3, 0.9), seed=10),
+        dict(id=10, arrival=0.02, d=3, n=(10, 9, 8), M=4, steps=12, velocity=(0.7, 0.2, -0.4), seed=11),
     ]
     for s in specs:
         s["dt"] = 0.5 / (max(s["n"]) * max(abs(v) for v in s["velocity"]))
