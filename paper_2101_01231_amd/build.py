@@ -21,6 +21,9 @@ ARCH = os.environ.get("RIDG_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function", "-I", os.path.join(HERE, "..", "include")]
 DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
+# per-unit device flags: the MFMA kernels keep their loop-carried accumulators in VGPRs (the
+# default AGPR form copies them in and out around every tap and waits for the MFMA chain)
+UNIT_FLAGS = {"k_mfma.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _run(cmd):
@@ -49,7 +52,7 @@ def build(force=True):
             cmd = [HIPCC, "-x", "c++", *COMMON, "-I", os.path.join(ROCM, "include"), "-D__HIP_PLATFORM_AMD__",
                    "-c", path, "-o", obj]
         elif src.endswith(".hip"):
-            cmd = [HIPCC, "-x", "hip", *COMMON, *DEVICE, "-c", path, "-o", obj]
+            cmd = [HIPCC, "-x", "hip", *COMMON, *DEVICE, *UNIT_FLAGS.get(src, []), "-c", path, "-o", obj]
         else:
             continue
         objs.append(obj)

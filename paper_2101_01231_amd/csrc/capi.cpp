@@ -870,7 +870,7 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
               for (int t = 0; t < d.ntaps && t < kBatchTaps; ++t)
                 for (int i = 0; i < 3; ++i) d.taps[t][i] = (int8_t)tl[3 * t + i];
               for (int i = 0; i < 3; ++i) d.n[i] = h->P.n[i];
-              d.tiles_per_group = mfma_tiles_per_group(h->P.nel);
+              d.tiles_per_group = mfma_tiles_per_group(h->P.nel, 0);
               d.group_begin = groups;
               groups += ((h->P.nel + 15) / 16 + d.tiles_per_group - 1) / d.tiles_per_group;
             }

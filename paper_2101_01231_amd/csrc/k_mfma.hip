@@ -22,7 +22,7 @@ namespace ridg {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-constexpr int kMfmaWaves = 4;
+constexpr int kMfmaWaves = 8;
 
 // One wavefront: column tiles tile = t_begin + first, t_begin + first + stride, ... < t_end of the
 // product out = base + sum_t A_t in_{e+off_t}; A fragments at fsrc (LDS or global).
@@ -36,28 +36,57 @@ __device__ inline void mfma_tiles(const DevGeom& g, const double* __restrict__ i
   const int kq = lane >> 4;  // K index within a chunk (B) / row group (D)
   const int col = lane & 15;
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  // rows of whole tiles (n0 a multiple of 16): a tile lies in one x-row, so the y and z parts of
+  // every neighbour index are wave-uniform and only the x wrap is per lane
+  const bool rows = g.n0 % 16 == 0;
   for (int64_t tile = t_begin + first; tile < t_end; tile += stride) {
     const int64_t e = tile * 16 + col;
     const bool valid = e < nel;
     int idx[3];
     elem_idx(g, valid ? e : nel - 1, idx);
+    int yz[2] = {0, 0};  // uniform y, z of the tile (rows only)
+    if (rows) {
+      yz[0] = __builtin_amdgcn_readfirstlane(idx[1]);
+      yz[1] = __builtin_amdgcn_readfirstlane(idx[2]);
+    }
     v4d acc[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) acc[mt] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int t = 0; t < ntaps; ++t) {
-      const int64_t ne = (int64_t)wrap(idx[0] + taps.off[t][0], g.n0) +
-                         (int64_t)g.n0 * ((int64_t)wrap(idx[1] + taps.off[t][1], g.n1) +
-                                          (int64_t)g.n1 * wrap(idx[2] + taps.off[t][2], g.n2));
-      const double* ft = fsrc + (size_t)t * CQ * 64 + lane;
+    auto nbr = [&](int t) -> int64_t {
+      if (rows) {
+        const int64_t row = (int64_t)wrap(yz[0] + taps.off[t][1], g.n1) + (int64_t)g.n1 * wrap(yz[1] + taps.off[t][2], g.n2);
+        return (int64_t)wrap(idx[0] + taps.off[t][0], g.n0) + (int64_t)g.n0 * row;
+      }
+      return (int64_t)wrap(idx[0] + taps.off[t][0], g.n0) +
+             (int64_t)g.n0 * ((int64_t)wrap(idx[1] + taps.off[t][1], g.n1) + (int64_t)g.n1 * wrap(idx[2] + taps.off[t][2], g.n2));
+    };
+    // B operands of one tap: column 4 q + kq of the neighbour (columns past C meet zero rows of
+    // A; the load index is clamped to stay inside `in`)
+    auto load_b = [&](int t, double (&b)[CQ]) {
+      const int64_t ne = nbr(t);
 #pragma unroll
       for (int q = 0; q < CQ; ++q) {
         const int c = 4 * q + kq;
-        // columns past C meet zero rows of A; the load index is clamped to stay inside `in`
-        const double v = in[(int64_t)(c < C ? c : C - 1) * nel + ne];
-        const double b = c < C ? v : 0.0;
+        b[q] = in[(int64_t)(c < C ? c : C - 1) * nel + ne];
+      }
+    };
+    double b[CQ];
+    load_b(0, b);
+    for (int t = 0; t < ntaps; ++t) {
+      double bn[CQ];  // the next tap's operands are requested before this tap's products
+      const bool more = t + 1 < ntaps;
+      if (more) load_b(t + 1, bn);
+      const double* ft = fsrc + (size_t)t * CQ * 64 + lane;
+#pragma unroll
+      for (int q = 0; q < CQ; ++q) {
+        const double bq = 4 * q + kq < C ? b[q] : 0.0;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ft[((size_t)mt * ntaps * CQ + q) * 64], b, acc[mt], 0, 0, 0);
+          acc[mt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ft[((size_t)mt * ntaps * CQ + q) * 64], bq, acc[mt], 0, 0, 0);
+      }
+      if (more) {
+#pragma unroll
+        for (int q = 0; q < CQ; ++q) b[q] = bn[q];
       }
     }
     if (valid) {
@@ -138,7 +167,7 @@ static int launch_rc(const DevGeom& g, const double* in, const double* base, dou
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   const int64_t ntiles = (nel + 15) / 16;
   // enough workgroups to fill the chip several times over; each sweeps a contiguous tile range
-  const int64_t per = mfma_tiles_per_group(nel);
+  const int64_t per = mfma_tiles_per_group(nel, in_lds ? lds : 0);
   const int64_t groups = (ntiles + per - 1) / per;
   if (in_lds)
     hipLaunchKernelGGL((tap_mfma_kernel<R, C, true>), dim3((unsigned)groups), dim3(64 * kMfmaWaves), lds,
@@ -165,10 +194,14 @@ int launch_tap_mfma(int d, int M, int kind, const DevGeom& g, const double* in, 
   return dispatch_dm<MfmaL>(d, M, kind, g, in, base, out, frag, taps, ntaps, stream);
 }
 
-int mfma_tiles_per_group(int64_t nel) {
+int mfma_tiles_per_group(int64_t nel, size_t lds_bytes) {
+  // one round of resident workgroups: up to 8 per CU, fewer when the staged fragments fill the LDS
+  int64_t resident = 8;
+  if (lds_bytes > 0 && (int64_t)(kMfmaMaxLds / lds_bytes) < resident) resident = (int64_t)(kMfmaMaxLds / lds_bytes);
+  if (resident < 1) resident = 1;
   const int64_t ntiles = (nel + 15) / 16;
   int64_t groups = (ntiles + kMfmaWaves - 1) / kMfmaWaves;
-  if (groups > 256 * 8) groups = 256 * 8;
+  if (groups > 256 * resident) groups = 256 * resident;
   return (int)((ntiles + groups - 1) / groups);
 }
 

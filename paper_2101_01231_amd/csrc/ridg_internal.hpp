@@ -240,7 +240,7 @@ struct BatchMfmaArgs {
 struct BatchMfmaTaps {
   int8_t off[kBatchTaps][3];
 };
-int mfma_tiles_per_group(int64_t nel);  // the tile range a workgroup sweeps (same split alone and batched)
+int mfma_tiles_per_group(int64_t nel, size_t lds_bytes);  // tiles a workgroup sweeps (fragments staged: lds_bytes)
 int launch_batch_mfma(int d, int M, int kind, const BatchMfmaArgs& args, int64_t groups, void* stream);
 
 // Launchers (defined in the k_*.hip units). All return a hipError_t as int.
