@@ -10,11 +10,12 @@ namespace ridg {
 
 template <int D, int M>
 __global__ __launch_bounds__(256) void batch_predict_kernel(BatchArgs args) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   int r = 0;
   for (int q = 1; q < args.count; ++q)
-    if ((int64_t)blockIdx.x >= args.d[q].block_begin) r = q;
+    if (blk >= args.d[q].block_begin) r = q;
   const BatchDesc& bd = args.d[r];
-  const int64_t e = ((int64_t)blockIdx.x - bd.block_begin) * 256 + threadIdx.x;
+  const int64_t e = (blk - bd.block_begin) * 256 + threadIdx.x;
   if (e >= bd.nel) return;
   DevGeom g{};
   g.d = D;
@@ -39,11 +40,12 @@ struct BatchTaps {
 template <int D, int M>
 __global__ __launch_bounds__(256) void batch_correct_kernel(BatchArgs args) {
   constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   int r = 0;
   for (int q = 1; q < args.count; ++q)
-    if ((int64_t)blockIdx.x >= args.d[q].block_begin) r = q;
+    if (blk >= args.d[q].block_begin) r = q;
   const BatchDesc& bd = args.d[r];
-  const int64_t e = ((int64_t)blockIdx.x - bd.block_begin) * 256 + threadIdx.x;
+  const int64_t e = (blk - bd.block_begin) * 256 + threadIdx.x;
   if (e >= bd.nel) return;
   DevGeom g{};
   g.d = D;

@@ -9,7 +9,7 @@ __global__ __launch_bounds__(256) void correct_kernel(DevGeom g, double dt, cons
                                                       const double* __restrict__ W, double* __restrict__ Qout,
                                                       DevTensors t) {
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (e >= nel) return;
   correct_elem<D, M, AFFINE>(g, dt, Q, W, Qout, t, e, nel);
 }

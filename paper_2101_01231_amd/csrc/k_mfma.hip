@@ -121,7 +121,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, co
   }
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   const int64_t ntiles = (nel + 15) / 16;
-  const int64_t t_begin = (int64_t)blockIdx.x * tiles_per_group;
+  const int64_t t_begin = xcd_block(blockIdx.x, gridDim.x) * tiles_per_group;
   const int64_t t_end = t_begin + tiles_per_group < ntiles ? t_begin + tiles_per_group : ntiles;
   mfma_tiles<R, C>(g, in, base, out, fsrc, taps, ntaps, t_begin, t_end, threadIdx.x >> 6, kMfmaWaves);
 }
@@ -131,9 +131,10 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void tap_mfma_kernel(DevGeom g, co
 // problem's result does not depend on what it is batched with. Fragments are read through the caches.
 template <int R, int C>
 __global__ __launch_bounds__(64 * kMfmaWaves) void batch_mfma_kernel(BatchMfmaArgs args) {
+  const int64_t blk = xcd_block(blockIdx.x, gridDim.x);
   int r = 0;
   for (int q = 1; q < args.count; ++q)
-    if ((int64_t)blockIdx.x >= args.d[q].group_begin) r = q;
+    if (blk >= args.d[q].group_begin) r = q;
   const BatchMfmaDesc& bd = args.d[r];
   DevGeom g{};
   g.n0 = bd.n[0];
@@ -141,7 +142,7 @@ __global__ __launch_bounds__(64 * kMfmaWaves) void batch_mfma_kernel(BatchMfmaAr
   g.n2 = bd.n[2];
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
   const int64_t ntiles = (nel + 15) / 16;
-  const int64_t t_begin = ((int64_t)blockIdx.x - bd.group_begin) * bd.tiles_per_group;
+  const int64_t t_begin = (blk - bd.group_begin) * bd.tiles_per_group;
   const int64_t t_end = t_begin + bd.tiles_per_group < ntiles ? t_begin + bd.tiles_per_group : ntiles;
   BatchMfmaTaps tp;
 #pragma unroll

@@ -22,7 +22,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PlanCfg<D, 
   const int seg = tail ? 0 : lane / SEGW;
   const int k = tail ? lane - S * SEGW : lane % SEGW;
   const bool idle = tail || k >= NT;   // no row (tail lanes, padding rows of a padded segment)
-  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S;
+  const int64_t wave_first = (xcd_block(blockIdx.x, gridDim.x) * C::WAVES + wave) * S;
   if (wave_first >= n_items) return;  // whole wavefront idle (the list is padded to S)
   int addr[LB > 0 ? LB : 1];
 #pragma unroll
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void predict_plans2_kernel(DevGeom g, double d
   const int seg = tail ? 0 : lane / SEGW;
   const int k = tail ? lane - S * SEGW : lane % SEGW;
   const bool idle = tail || k >= NT;
-  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S * 2;
+  const int64_t wave_first = (xcd_block(blockIdx.x, gridDim.x) * C::WAVES + wave) * S * 2;
   if (wave_first >= n_items) return;  // the list is padded to 2 S
   int addr[LB > 0 ? LB : 1];
 #pragma unroll
@@ -234,7 +234,7 @@ predict_plans_nr_kernel(DevGeom g, double dt, const double* __restrict__ Q, doub
   bool idle[RPL];
 #pragma unroll
   for (int u = 0; u < RPL; ++u) idle[u] = tail || k + u * SEGW >= NT;
-  const int64_t wave_first = ((int64_t)blockIdx.x * C::WAVES + wave) * S;
+  const int64_t wave_first = (xcd_block(blockIdx.x, gridDim.x) * C::WAVES + wave) * S;
   if (wave_first >= n_items) return;  // the list is padded to S
   int addr[LB > 0 ? LB : 1];
 #pragma unroll

@@ -11,7 +11,7 @@ __global__ __launch_bounds__(256) void predict_prefactored_kernel(DevGeom g, con
                                                                   const double* __restrict__ G, Taps taps,
                                                                   int ntaps) {
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (e >= nel) return;
   predict_prefactored_elem<D, M>(g, Q, W, G, taps, ntaps, e, nel);
 }
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(256) void tap_update_kernel(DevGeom g, const double
                                                          const double* __restrict__ base, double* __restrict__ out,
                                                          const double* __restrict__ A, TapsN taps, int ntaps) {
   const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
   if (e >= nel) return;
   tap_update_elem<R, C>(g, in, base, out, A, taps, ntaps, e, nel);
 }

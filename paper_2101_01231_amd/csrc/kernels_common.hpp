@@ -31,6 +31,16 @@ __host__ __device__ constexpr int seg_width(int nt) {
 }
 
 // ---------------------------------------------------------------- geometry helpers
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD b % 8), each XCD with
+// its own L2. This bijection of [0, n) gives XCD x the contiguous logical range
+// [x q + min(x, r), ...) (q = n / 8, r = n % 8), so neighbouring elements, whose data the stencils
+// and region gathers share, are processed under one L2.
+__device__ inline int64_t xcd_block(int64_t b, int64_t n) {
+  constexpr int64_t X = 8;
+  const int64_t q = n / X, r = n % X, x = b % X;
+  return x * q + (x < r ? x : r) + b / X;
+}
+
 __device__ inline void elem_idx(const DevGeom& g, int64_t e, int idx[3]) {
   idx[0] = (int)(e % g.n0);
   int64_t r = e / g.n0;
