@@ -139,11 +139,42 @@ def test_rotation_full_size_sampled():
     sim = ridg.Simulation(lib_problem(2, wl.n, wl.M, wl.velocity))
     # the rotation centre and the periodic corner are the two circulation points: 4 cyclic regions each
     assert sim.info.n_tear_elements == 8 and sim.info.n_dense_elements == 0
+    refs = np.array([ref[e] for e in el])
+    # every segment layout of the region-solve kernel, then the autotuned configuration bench.py times
+    for lay in range(5):
+        print(f"[gpu] rotation 512^2 layout {lay}", flush=True)
+        sim.set_option(ridg.OPT_PLAN_LAYOUT, lay)
+        sim.set_state(q0)
+        sim.step(1, wl.dt)
+        assert rel_l2(sim.get_state()[el], refs) <= TOL, lay
     sim.set_state(q0)
+    sim.autotune(wl.dt, steps=4)
+    sim.set_option(ridg.OPT_GRAPH, 0)
     sim.step(1, wl.dt)
     got = sim.get_state()
     sim.close()
-    assert rel_l2(got[el], np.array([ref[e] for e in el])) <= TOL
+    assert rel_l2(got[el], refs) <= TOL
+
+
+def _const_full_size(d, wl, el, ref):
+    """One step in each constant-velocity kernel configuration, and autotuned as bench.py runs it."""
+    refs = np.array([ref[e] for e in el])
+    sim = ridg.Simulation(lib_problem(d, wl.n, wl.M, wl.velocity))
+    for comp in (0, 1):
+        for mfma in (0, 1):
+            print(f"[gpu] {wl.name} composite={comp} mfma={mfma}", flush=True)
+            sim.set_option(ridg.OPT_COMPOSITE, comp)
+            sim.set_option(ridg.OPT_MFMA, mfma)
+            sim.set_state(wl.q0)
+            sim.step(1, wl.dt)
+            assert rel_l2(sim.get_state()[el], refs) <= TOL, (comp, mfma)
+    sim.set_state(wl.q0)
+    sim.autotune(wl.dt, steps=4)
+    sim.set_option(ridg.OPT_GRAPH, 0)
+    sim.step(1, wl.dt)
+    got = sim.get_state()
+    sim.close()
+    assert rel_l2(got[el], refs) <= TOL
 
 
 def test_advection_3d_full_size_sampled():
@@ -152,8 +183,7 @@ def test_advection_3d_full_size_sampled():
     rng = np.random.default_rng(5)
     el = _sample(prob, rng, 12, [0, prob.n_el - 1])
     ref = S.step_sampled(prob, wl.q0, wl.dt, el)
-    got = run_gpu(3, wl.n, wl.M, wl.velocity, wl.q0, wl.dt, 1)
-    assert rel_l2(got[el], np.array([ref[e] for e in el])) <= TOL
+    _const_full_size(3, wl, el, ref)
 
 
 def test_advection_2d_full_size_sampled():
@@ -162,8 +192,7 @@ def test_advection_2d_full_size_sampled():
     rng = np.random.default_rng(6)
     el = _sample(prob, rng, 24, [0, prob.n_el - 1])
     ref = S.step_sampled(prob, wl.q0, wl.dt, el)
-    got = run_gpu(2, wl.n, wl.M, wl.velocity, wl.q0, wl.dt, 1)
-    assert rel_l2(got[el], np.array([ref[e] for e in el])) <= TOL
+    _const_full_size(2, wl, el, ref)
 
 
 def test_conservation_determinism_checkpoint():
