@@ -29,7 +29,7 @@ sys.path.insert(0, HERE)
 
 FP64_VECTOR_PEAK_TFLOPS = 78.6  # MI355X: 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak (same as the vector peak on this part)
-FP32_VECTOR_PEAK_TFLOPS = 157.3  # published FP32 vector peak (counts packed FP32, which this build does not use)
+FP32_VECTOR_PEAK_TFLOPS = 157.3  # published FP32 vector peak (counts packed FP32, which the kernels do not use)
 HBM_PEAK_GBS = 8000.0
 METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error; p99 latency"
 
@@ -336,7 +336,7 @@ def main():
     if args.counter_summary:
         return counter_summary(args)
     if args.gpus != 1:
-        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+        print(f"bench.py measures one GPU: the library has no multi-GPU path (asked for --gpus {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     from paper_2101_01231_amd import ridg
