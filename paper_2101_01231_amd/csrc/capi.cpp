@@ -48,7 +48,7 @@ struct Layout {
 
 size_t tensor_doubles(const RefTensors& T) {
   return T.Tt.size() + T.Cc.size() + T.Bv.size() + T.Fo.size() + T.Fn.size() + T.Cv.size() + T.CFo.size() +
-         T.CFn.size();
+         T.CFn.size() + T.Cown.size();
 }
 
 // Element work lists of the REGION solver, grouped by plan and padded so that a wavefront never
@@ -431,6 +431,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->dt.Cv = push(T.Cv);
   h->dt.CFo = push(T.CFo);
   h->dt.CFn = push(T.CFn);
+  h->dt.Cown = push(T.Cown);
   h->geom = make_geom(P);
   int err = hipMemcpyAsync(base, tens.data(), tens.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err && P.solver == RIDG_SOLVER_REGION) {

@@ -204,6 +204,19 @@ RefTensors make_tensors(const Basis& B) {
       }
     }
   }
+  // volume term minus the faces that take the element's own trace, per set of such faces
+  T.Cown.assign((size_t)d * np * 4 * ns * nt, 0.0);
+  for (int i = 0; i < d; ++i)
+    for (int p = 0; p < np; ++p)
+      for (int bits = 0; bits < 4; ++bits) {
+        double* C = &T.Cown[T.cown(i, p, bits)];
+        for (size_t q = 0; q < (size_t)ns * nt; ++q) {
+          double v = T.Cv[T.cv(i, p) + q];
+          if (bits & 1) v -= T.CFo[T.cf(i, -1, p) + q];
+          if (bits & 2) v -= T.CFo[T.cf(i, 1, p) + q];
+          C[q] = v;
+        }
+      }
   return T;
 }
 

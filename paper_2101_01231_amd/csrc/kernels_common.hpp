@@ -329,12 +329,23 @@ __device__ inline void seg_solve_nr(double (&a)[C::RPL][C::NT], double (&rhs)[C:
       key = seg_max_rot<SEGW, C::LB>(key, addr);
     const int p = (int)(LMASK - (key & LMASK));
     bool pivu[RPL];
+    bool anyp = false;
+    double pval = a[0][c];
 #pragma unroll
     for (int u = 0; u < RPL; ++u) {
       pivu[u] = (p == k + u * SEGW) && !idle[u];
+      anyp = anyp || pivu[u];
+      if (u > 0) pval = pivu[u] ? a[u][c] : pval;
+    }
+    // one reciprocal for whichever row of the lane holds the pivot (the row branches below then
+    // only store, instead of each running its own reciprocal chain one after the other)
+    double pinv = 0.0;
+    if (anyp) pinv = recip(pval);
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
       if (pivu[u]) {
-        inv[u] = recip(a[u][c]);
-        publish_row<off, c + 1, NT>(pbase, a[u], rhs[u], inv[u]);
+        inv[u] = pinv;
+        publish_row<off, c + 1, NT>(pbase, a[u], rhs[u], pinv);
         used[u] = true;
         step[u] = c;
       }
@@ -517,6 +528,26 @@ static int dispatch_dm(int d, int M, Args... args) {
 static inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
 // ---------------------------------------------------------------- correction (per element)
+// acc += sum_p V_ip Cown[i][p][bits] w (volume minus own-trace faces of direction i)
+template <int D, int M, bool AFFINE>
+__device__ inline void own_term(const double* cown, int i, int bits, const double (&V)[D][D + 1],
+                                const double (&w)[n_spacetime(D, M)], double (&acc)[n_space(D, M)]) {
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NP = D + 1;
+#pragma unroll 1
+  for (int p = 0; p < NP; ++p) {
+    if (p == 1 + i || (!AFFINE && p > 0)) continue;
+    const double vp = V[i][p];
+    const double* cv = cown + (((size_t)i * NP + p) * 4 + bits) * NS * NT;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) s = fma(cv[k * NT + l], w[l], s);
+      acc[k] = fma(vp, s, acc[k]);
+    }
+  }
+}
+
 // acc -= sum_p V_ip tens[i][sd][p] w (the face term of direction i, side sd)
 template <int D, int M, bool AFFINE>
 __device__ inline void face_term(const double* tens, int i, int sd, const double (&V)[D][D + 1],
@@ -553,36 +584,25 @@ __device__ inline void correct_elem(const DevGeom& g, double dt, const double* Q
   for (int k = 0; k < NS; ++k) acc[k] = 0.0;
 #pragma unroll 1
   for (int i = 0; i < D; ++i) {
+    const int side_m = face_side<D>(g, idx, i, -1), side_p = face_side<D>(g, idx, i, 1);
+    const int bits = (side_m == 0 ? 1 : 0) | (side_p == 0 ? 2 : 0);
+    // volume term and the faces that take the element's own trace: one precombined tensor per
+    // (velocity mode, own-face set); one branch per set keeps the tensor pointer wave-uniform
+    // (scalar loads), and a wavefront whose elements differ runs each set on its own lanes
 #pragma unroll 1
-    for (int p = 0; p < NP; ++p) {
-      if (p == 1 + i || (!AFFINE && p > 0)) continue;
-      const double vp = V[i][p];
-      const double* cv = t.Cv + ((size_t)i * NP + p) * NS * NT;
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int l = 0; l < NT; ++l) s = fma(cv[k * NT + l], we[l], s);
-        acc[k] = fma(vp, s, acc[k]);
-      }
-    }
+    for (int b = 0; b < 4; ++b)
+      if (bits == b) own_term<D, M, AFFINE>(t.Cown, i, b, V, we, acc);
+    // faces that take the upwind neighbour's trace
 #pragma unroll 1
     for (int sd = 0; sd < 2; ++sd) {
-      const int s = sd ? 1 : -1;
-      const int side = face_side<D>(g, idx, i, s);
-      // two branches with wave-uniform tensor pointers (scalar loads); a wavefront whose elements
-      // disagree on the face's upwind side runs both, each on its own lanes
-      if (side == 0) {
-        face_term<D, M, AFFINE>(t.CFo, i, sd, V, we, acc);
-      } else {
-        int j[3] = {idx[0], idx[1], idx[2]};
-        j[i] += s;
-        const int64_t en = elem_lin(g, j[0], j[1], j[2]);
-        double wn[NT];
+      if ((sd ? side_p : side_m) == 0) continue;
+      int j[3] = {idx[0], idx[1], idx[2]};
+      j[i] += sd ? 1 : -1;
+      const int64_t en = elem_lin(g, j[0], j[1], j[2]);
+      double wn[NT];
 #pragma unroll
-        for (int l = 0; l < NT; ++l) wn[l] = W[(int64_t)l * nel + en];
-        face_term<D, M, AFFINE>(t.CFn, i, sd, V, wn, acc);
-      }
+      for (int l = 0; l < NT; ++l) wn[l] = W[(int64_t)l * nel + en];
+      face_term<D, M, AFFINE>(t.CFn, i, sd, V, wn, acc);
     }
   }
   constexpr double scale = 1.0 / (double)(1 << D);

@@ -43,10 +43,12 @@ struct RefTensors {
   std::vector<double> Cv;   // [i][p][k][l]      int d_i Phi_k Psi_p Psi_l (ns x nt)
   std::vector<double> CFo;  // [i][s][p][k][l]   s int Phi_k|s Psi_p Psi_l|s
   std::vector<double> CFn;  // [i][s][p][k][l]   s int Phi_k|s Psi_p Psi_l|-s
+  std::vector<double> Cown; // [i][p][bits][k][l] Cv - CFo of the faces in bits (bit 0: s = -1, bit 1: s = +1)
   size_t bv(int i, int p) const { return ((size_t)i * np + p) * nt * nt; }
   size_t f(int i, int s, int p) const { return (((size_t)i * 2 + (s > 0)) * np + p) * nt * nt; }
   size_t cv(int i, int p) const { return ((size_t)i * np + p) * ns * nt; }
   size_t cf(int i, int s, int p) const { return (((size_t)i * 2 + (s > 0)) * np + p) * ns * nt; }
+  size_t cown(int i, int p, int bits) const { return (((size_t)i * np + p) * 4 + bits) * ns * nt; }
 };
 RefTensors make_tensors(const Basis& b);
 
@@ -162,6 +164,7 @@ struct DevTensors {  // device copies (FP64), offsets into one buffer
   const double* Cv;
   const double* CFo;
   const double* CFn;
+  const double* Cown;
 };
 
 // Precombined region-block tensors of the upwind-plan kernel. For an affine velocity the
