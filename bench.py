@@ -105,7 +105,9 @@ def traffic_from_profiles(kernel):
                 if not line.startswith(RECORD_TAG):
                     continue
                 rec = json.loads(line[len(RECORD_TAG):])
-                if rec["kernel"].startswith(kernel) and rec["src"] == want:
+                # the profiler's name may carry further template arguments (e.g. where operands live)
+                same = rec["kernel"] == kernel or (kernel.endswith(">") and rec["kernel"].startswith(kernel[:-1] + ","))
+                if same and rec["src"] == want:
                     return {"bytes": rec["fetch_bytes"] + rec["write_bytes"], "fetch_bytes": rec["fetch_bytes"],
                             "write_bytes": rec["write_bytes"], "source": os.path.basename(path)}
     return None
