@@ -572,7 +572,7 @@ __device__ inline void face_term(const double* tens, int i, int sd, const double
 template <int D, int M, bool AFFINE>
 __device__ inline void correct_elem(const DevGeom& g, double dt, const double* Q, const double* W, double* Qout,
                                     const DevTensors& t, int64_t e, int64_t nel) {
-  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NP = D + 1;
+  constexpr int NS = n_space(D, M), NT = n_spacetime(D, M);
   int idx[3];
   elem_idx(g, e, idx);
   double V[D][D + 1];
