@@ -85,7 +85,18 @@ BAD = [
     (dict(dim=2, n=(8, 8), order=2, velocity=(float("nan"), 1)), ridg.RIDG_E_INVAL),
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), precision=7), ridg.RIDG_E_INVAL),
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), refine_steps=9), ridg.RIDG_E_INVAL),
+    (dict(dim=1, n=((1 << 20) + 1,), order=2, velocity=(1,)), ridg.RIDG_E_INVAL),  # axis above 2^20
+    (dict(dim=3, n=(2048, 2048, 1024), order=1, velocity=(1, 1, 1)), ridg.RIDG_E_INVAL),  # 2^32 elements
 ]
+
+
+def test_largest_accepted_sizes():
+    """Maximum sizes: a 2^20-element axis at the highest order, and 2^31 elements in all."""
+    for case in (dict(dim=1, n=(1 << 20,), order=5, velocity=(1.0,)),
+                 dict(dim=3, n=(2048, 1024, 1024), order=1, velocity=(1.0, 1.0, 1.0))):
+        nbytes = ridg.workspace_bytes(ridg.make_problem(**case))
+        nel = int(np.prod(case["n"]))
+        assert nbytes > 2 * nel * 8  # two state buffers at least
 
 
 @pytest.mark.parametrize("case,code", BAD)
