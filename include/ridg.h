@@ -64,13 +64,13 @@ extern "C" {
 
 /* arithmetic of the prediction (the correction is always FP64) */
 #define RIDG_FP64 0
-#define RIDG_FP32_REFINE 1 /* FP32 region solves + FP64-residual iterative refinement */
+#define RIDG_FP32_REFINE 1 /* FP32 region solves + FP64-residual iterative refinement (RIDG_SOLVER_REGION) */
 
 /* region solver */
 #define RIDG_SOLVER_AUTO 0        /* PREFACTORED for RIDG_FLUX_CONST, REGION otherwise */
 #define RIDG_SOLVER_PREFACTORED 1 /* constant v only: W = G Q_region with G = E_c A^-1 C from a host FP64 LU */
 #define RIDG_SOLVER_REGION 2      /* per element: assemble (QQF) and solve the region system by upwind block
-                                     elimination with pivoted dense LU per block; regions whose centre lies on
+                                     elimination, Gauss-Jordan with partial pivoting per block; regions whose centre lies on
                                      a dependency cycle tear one block (multi-right-hand-side elimination plus
                                      one block-sized system), else use the dense path */
 #define RIDG_SOLVER_DENSE 3       /* per element: dense pivoted LU of the whole 3^d theta_T region system */
@@ -114,7 +114,7 @@ typedef struct ridg_info {
 /* Accumulated stage times of ridg_step, from HIP events recorded on the handle's stream. */
 typedef struct ridg_timing {
   int64_t steps;     /* steps timed since the last ridg_get_timing */
-  double predict_ms; /* sum over steps: prediction kernels (rows a1-a5) */
+  double predict_ms; /* sum over steps: prediction kernels (region gather, assembly, solve) */
   double correct_ms; /* sum over steps: correction kernel */
   double max_step_ms; /* slowest single step (prediction + correction) */
 } ridg_timing;

@@ -103,7 +103,7 @@ def test_rotation_small(n, M, solver):
     (3, (4, 5, 3), 2, ("const", (0.5, 1.0, -0.5))),
 ])
 def test_prediction_parity(d, n, M, vel):
-    """Rows a1-a5 alone: the centre predictions W against the oracle's region solves."""
+    """The prediction alone: the centre predictions W against the oracle's region solves."""
     prob = oracle_problem(d, n, M, vel)
     q0 = I.random_state(d, n, M, seed=99)
     dt = 0.4 * min(prob.h) / (0.5 if vel[0] == "rotation" else max(abs(x) for x in vel[1]))
@@ -125,7 +125,8 @@ def _sample(prob, rng, count, extra=()):
 
 def test_rotation_full_size_sampled():
     """512x512, order 4, rotation about (1/2, 1/2): one step, sampled elements (including the
-    regions around the rotation centre, which take the dense path) against the oracle."""
+    cyclic regions around the rotation centre and the periodic corner, solved by tearing) against
+    the oracle."""
     wl = I.rotation_2d()
     n = wl.n[0]
     prob = oracle_problem(2, wl.n, wl.M, wl.velocity)
