@@ -34,14 +34,15 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error; p99 latency"
 
 
-# translation unit of each kernel family: a counter record is valid while these sources are unchanged
-KERNEL_UNITS = {"predict_plans2_kernel": "k_plans.hip", "predict_plans_nr_kernel": "k_plans.hip",
-                "predict_plans_kernel": "k_plans.hip",
-                "predict_prefactored_kernel": "k_prefactored.hip", "tap_update_kernel": "k_prefactored.hip",
-                "fused_prefactored_kernel": "k_prefactored.hip", "correct_kernel": "k_correct.hip",
-                "predict_tear_kernel": "k_tear_dense.hip", "predict_dense_kernel": "k_tear_dense.hip",
-                "batch_predict_kernel": "k_batch.hip", "batch_correct_kernel": "k_batch.hip",
-                "tap_mfma_kernel": "k_mfma.hip"}
+# source files of each kernel family: a counter record is valid while these sources are unchanged
+KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
+                "predict_plans_nr_kernel": ["plans_nr.hpp", "k_plans_nr.hip", "k_plans_dpp.hip"],
+                "predict_plans_kernel": ["k_plans.hip"],
+                "predict_prefactored_kernel": ["k_prefactored.hip"], "tap_update_kernel": ["k_prefactored.hip"],
+                "fused_prefactored_kernel": ["k_prefactored.hip"], "correct_kernel": ["k_correct.hip"],
+                "predict_tear_kernel": ["k_tear_dense.hip"], "predict_dense_kernel": ["k_tear_dense.hip"],
+                "batch_predict_kernel": ["k_batch.hip"], "batch_correct_kernel": ["k_batch.hip"],
+                "tap_mfma_kernel": ["k_mfma.hip"]}
 RECORD_TAG = "traffic-record: "
 
 
@@ -51,7 +52,7 @@ def kernel_source_hash(kernel):
     if fam is None:
         return None
     h = hashlib.sha256()
-    for f in (KERNEL_UNITS[fam], "kernels_common.hpp", "ridg_internal.hpp"):
+    for f in (*KERNEL_UNITS[fam], "kernels_common.hpp", "ridg_internal.hpp"):
         with open(os.path.join(HERE, "paper_2101_01231_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

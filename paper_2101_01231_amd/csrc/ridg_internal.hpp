@@ -266,7 +266,16 @@ int launch_predict_plans(int d, int M, int layout, int precision, int refine, co
 // plan-kernel segment layouts: 0 packed, 1 padded to a power of two, 2 two regions per packed
 // segment, 3 two rows per lane, 4 several rows per lane in power-of-two (DPP) segments
 constexpr int kLayouts = 5;
-int items_per_wave(int d, int M, int layout);  // work-list padding multiple (regions a wavefront takes at once)
+int items_per_wave(int d, int M, int layout);
+// the FP64-only layouts (separate translation units)
+int launch_plans2(int d, int M, const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                  const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
+int launch_plans_2rows(int d, int M, const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                       const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
+                       void* stream);
+int launch_plans_dpp(int d, int M, const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
+                     const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
+                     void* stream);  // work-list padding multiple (regions a wavefront takes at once)
 // Whole run of n_steps on one workgroup (mesh state resident in LDS), constant velocity;
 // returns hipErrorInvalidValue when the mesh does not fit.
 int fused_fits(int d, int M, int64_t nel);
