@@ -6,10 +6,12 @@ whole mesh. Default workload: 2D solid-body rotation v = (-(y-1/2), x-1/2) on a
 modes per element, 180-unknown regions), CFL 0.5, seeded compact C-infinity bumps,
 FP64. Inputs are resident in HBM before the timed region starts.
 
-Prints one JSON line: space-time DOF-updates/s (elements * theta_T * steps / s),
-per-step p50/p99 latency, the roofline of the dominant kernel (prediction) from
-HIP events recorded by the library on its stream, and the plain CPU oracle timed on
-a bounded sample of the same workload.
+Prints one JSON line: space-time DOF-updates/s (elements * theta_T * steps / s) of the
+timed steps, run as one ridg_step call with the autotuned options (graph replay or
+one fused launch where those won); per-step p50/p99 latency and the roofline of the
+dominant kernel from a second pass of single steps timed with HIP events, around
+each step and, inside the library, around each stage on its stream; and the plain
+CPU oracle timed on a bounded sample of the same workload.
 """
 
 import argparse
@@ -245,34 +247,44 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     # autotuner (native, HIP events): picks segment layout / composite stencil / fused steps; graph
     # replay is then switched off so that the library's per-stage events cover the timed steps
     sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
-    sim.set_option(ridg.OPT_GRAPH, 0)
+    tuned = {"graph": sim.get_option(ridg.OPT_GRAPH), "fused": sim.get_option(ridg.OPT_FUSED)}
     opts = {"plan_layout": sim.get_option(ridg.OPT_PLAN_LAYOUT), "composite": sim.get_option(ridg.OPT_COMPOSITE),
-            "fused": sim.get_option(ridg.OPT_FUSED), "mfma": sim.get_option(ridg.OPT_MFMA)}
-    if opts["fused"]:
-        sim.set_option(ridg.OPT_FUSED, 0)  # one launch for all steps would hide the per-step latency
-        opts["fused"] = 0
+            "mfma": sim.get_option(ridg.OPT_MFMA), **tuned}
     print(f"[bench] {label}: {wl.name} n={wl.n} M={wl.M} solver={info.solver} plans={info.n_plans} "
-          f"tear={info.n_tear_elements} dense={info.n_dense_elements} warmup={warmup} steps={steps}",
+          f"tear={info.n_tear_elements} dense={info.n_dense_elements} warmup={warmup} steps={steps} opts={opts}",
           file=sys.stderr, flush=True)
+    stream = torch.cuda.current_stream()
+    # latency pass: one launch sequence per step (graph replay and fused steps off), HIP events around
+    # every step and, inside the library, around each stage
+    sim.set_option(ridg.OPT_GRAPH, 0)
+    sim.set_option(ridg.OPT_FUSED, 0)
     if warmup:
         sim.step(warmup, wl.dt)
     sim.synchronize()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
     sim.enable_timing(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
     for s in range(steps):
         starts[s].record(stream)
         sim.step(1, wl.dt)
         ends[s].record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     tim = sim.get_timing()
     sim.enable_timing(False)
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    # throughput pass, from the initial state again: the autotuned options, all timed steps in one call
+    sim.set_option(ridg.OPT_GRAPH, tuned["graph"])
+    sim.set_option(ridg.OPT_FUSED, tuned["fused"])
+    sim.set_state(wl.q0)
+    if warmup:
+        sim.step(warmup, wl.dt)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps, wl.dt)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
     q = sim.get_state()
     sim.close()
     pred_ms = tim.predict_ms / max(tim.steps, 1)
