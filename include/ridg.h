@@ -183,8 +183,9 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value);
 int ridg_get_option(ridg_t* h, int32_t option, int64_t* value);
 
 /* Autotuner: time every applicable option set on `steps` steps of size dt (host clock around a
- * run synchronised with the handle's stream; two sweeps over the option sets, each set keeping its
- * faster time), keep the fastest and restore the state. Synchronises the stream. Results are cached per problem shape
+ * run synchronised with the handle's stream, lengthened up to 64x while it lasts under 2 ms; two
+ * sweeps over the option sets, each set keeping its faster time), keep the fastest and restore the
+ * state. Synchronises the stream. Results are cached per problem shape
  * in the process and, when the environment variable RIDG_AUTOTUNE_CACHE names a file, appended to
  * that file and reused by later processes (*best_ms_per_step is then -1). */
 int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step);

@@ -1021,14 +1021,23 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
     rc = RIDG_OK;
     // host clock around a synchronised run: what a caller waits for, launch and graph overheads
     // included (events on the stream have ranked graph replays ahead of slower wall times)
-    err = hipStreamSynchronize(h->stream);
-    const auto t0 = std::chrono::steady_clock::now();
-    if (!err) rc = ridg_step(h, steps, dt);
+    // Steps of a few microseconds: the run is lengthened (4x at a time, up to 64x) until it lasts
+    // 2 ms, so that the synchronisation's own cost does not decide the ranking.
+    for (int n = steps; !err && !rc;) {
+      err = hipStreamSynchronize(h->stream);
+      const auto t0 = std::chrono::steady_clock::now();
+      if (!err) rc = ridg_step(h, n, dt);
+      if (rc < 0) break;
+      rc = RIDG_OK;
+      if (!err) err = hipStreamSynchronize(h->stream);
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (err || ms >= 2.0 || n >= 64 * steps) {
+        if (!err) cand_ms[c] = std::min(cand_ms[c], ms / n);
+        break;
+      }
+      n *= 4;
+    }
     if (rc < 0) break;
-    rc = RIDG_OK;
-    if (!err) err = hipStreamSynchronize(h->stream);
-    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    if (!err) cand_ms[c] = std::min(cand_ms[c], ms / steps);
     if (!err) err = hipMemcpyAsync(h->Q[cur0], h->stage, bytes, hipMemcpyDeviceToDevice, h->stream);
     h->cur = cur0;
   }

@@ -137,11 +137,11 @@ def test_composite_and_tap_correction_match_oracle(d, n, M, v):
 
 @pytest.mark.parametrize("d,n,M,v", [(3, (16, 9, 5), 3, (1.0, -0.7, 0.4)), (2, (33, 17), 4, (-1.0, 0.5)),
                                      (2, (40, 40), 5, (0.3, 0.9)), (1, (50,), 4, (0.8,)), (3, (5, 4, 6), 4, (0.2, 0.3, -0.9)),
-                                     (3, (6, 5, 7), 5, (0.5, -1.0, 0.3))])
+                                     (3, (6, 5, 7), 5, (0.5, -1.0, 0.3)), (2, (384, 384), 3, (1.0, 0.5))])
 def test_mfma_tap_kernels_match_vector_kernels(d, n, M, v):
     """FP64 MFMA tap kernels (prediction, correction, composite) against the vector kernels: ragged
     tile tails (element counts not multiples of 16), several row tiles (theta_T > 16), operators
-    too large for LDS (3D order 5, read through the caches)."""
+    too large for LDS (3D order 5, read through the caches), and a 384^2 mesh of 2304 workgroups."""
     p = ridg.make_problem(d, n, M, velocity=v)
     q0 = I.random_state(d, n, M, seed=11)
     dt = 0.4 * min(1.0 / k for k in n) / max(abs(x) for x in v)
