@@ -49,12 +49,13 @@ RECORD_TAG = "traffic-record: "
 
 
 def kernel_source_hash(kernel):
-    """sha256 of the sources a kernel is compiled from (its unit and the shared device headers)."""
+    """sha256 of the sources a kernel is compiled from (its unit, the shared device headers and the
+    build script that holds the compiler flags)."""
     fam = next((f for f in KERNEL_UNITS if f + "<" in kernel), None)
     if fam is None:
         return None
     h = hashlib.sha256()
-    for f in (*KERNEL_UNITS[fam], "kernels_common.hpp", "ridg_internal.hpp"):
+    for f in (*KERNEL_UNITS[fam], "kernels_common.hpp", "ridg_internal.hpp", os.path.join("..", "build.py")):
         with open(os.path.join(HERE, "paper_2101_01231_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -243,7 +244,10 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     prob = make_problem(wl, precision, solver, refine)
     sim = ridg.Simulation(prob, device="cuda:0")
     info = sim.info
-    sim.set_state(wl.q0)
+    # the initial state stays resident in HBM: restoring it from the host would leave the GPU idle
+    # for the copy, and its clocks ramp back up only over the first milliseconds of the timed steps
+    q0_dev = torch.from_numpy(np.ascontiguousarray(wl.q0, dtype=np.float64)).to("cuda:0")
+    sim.set_state(q0_dev)
     # autotuner (native, HIP events): picks segment layout / composite stencil / fused steps; graph
     # replay is then switched off so that the library's per-stage events cover the timed steps
     sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
@@ -276,7 +280,7 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     # throughput pass, from the initial state again: the autotuned options, all timed steps in one call
     sim.set_option(ridg.OPT_GRAPH, tuned["graph"])
     sim.set_option(ridg.OPT_FUSED, tuned["fused"])
-    sim.set_state(wl.q0)
+    sim.set_state(q0_dev)
     if warmup:
         sim.step(warmup, wl.dt)
     sim.synchronize()
