@@ -39,6 +39,7 @@ METRIC = "space-time DOF-updates/s (2D adv, M=4) vs plain FP64 at equal L2 error
 # source files of each kernel family: a counter record is valid while these sources are unchanged
 KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
                 "predict_plans_nr_kernel": ["plans_nr.hpp", "k_plans_nr.hip", "k_plans_dpp.hip"],
+                "predict_plans_sp_kernel": ["plans_nr.hpp", "k_plans_sp.hip"],
                 "predict_plans_kernel": ["k_plans.hip"],
                 "predict_prefactored_kernel": ["k_prefactored.hip"], "tap_update_kernel": ["k_prefactored.hip"],
                 "fused_prefactored_kernel": ["k_prefactored.hip"], "correct_kernel": ["k_correct.hip"],
@@ -80,10 +81,13 @@ def dominant_kernel(info, opts, precision):
         nt = info.theta_t
         if lay == 3:  # two rows per lane
             return f"ridg::predict_plans_nr_kernel<{d}, {M}, 2, {(nt + 1) // 2}>"
-        if lay == 4:  # rows per lane in power-of-two segments of >= theta_T / 3 lanes
+        if lay in (4, 5):  # rows per lane in power-of-two segments of >= theta_T / 3 lanes
             segw = 1
             while segw < (nt + 2) // 3:
                 segw *= 2
+            if lay == 5:  # static pivots
+                f32 = "true" if precision == "fp32" else "false"
+                return f"ridg::predict_plans_sp_kernel<{d}, {M}, {(nt + segw - 1) // segw}, {segw}, {f32}>"
             return f"ridg::predict_plans_nr_kernel<{d}, {M}, {(nt + segw - 1) // segw}, {segw}>"
         f32 = "true" if precision == "fp32" else "false"
         return f"ridg::predict_plans_kernel<{d}, {M}, {'true' if lay == 1 else 'false'}, {f32}>"

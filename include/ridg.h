@@ -3,8 +3,8 @@
  * predictor/corrector library (libridg.so, HIP kernels for gfx950).
  *
  * Method (arXiv 2101.01231): scalar conservation law q_t + div(v q) = 0
- * (Sec. 2.1) on a uniform periodic Cartesian mesh of the unit box [0,1]^d,
- * d = 1, 2, 3. Each step has two stages:
+ * (Sec. 2.1) on a uniform periodic Cartesian mesh of the box
+ * [0,L_1] x .. x [0,L_d] (the unit box by default), d = 1, 2, 3. Each step has two stages:
  *   prediction (Sec. 2.2, eq. pred_full_system): for every element, the
  *     space-time DG system on its region of 3^d vertex neighbours (upwind
  *     fluxes on faces inside the region, the region element's own trace on
@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RIDG_ABI_VERSION 1
+#define RIDG_ABI_VERSION 2
 
 /* return codes */
 #define RIDG_OK 0
@@ -55,12 +55,19 @@ extern "C" {
 #define RIDG_E_SINGULAR (-4)    /* zero pivot in a host FP64 factorisation */
 #define RIDG_E_NONFINITE (-5)   /* NaN/Inf in the input state */
 #define RIDG_E_UNSUPPORTED (-6) /* valid problem outside what the library implements */
-#define RIDG_W_UNSTABLE 1       /* CFL number dt*max|v_i|/h_i above 1: the step may be unstable */
+#define RIDG_W_UNSTABLE 1       /* constant velocity: the step's von Neumann amplification exceeds 1
+                                   (ridg_info.spectral_radius > 1 + 1e-10); affine velocity: the CFL
+                                   number dt max|v_i|/h_i exceeds 1 */
 
 /* velocity field kinds */
 #define RIDG_FLUX_CONST 0    /* v = velocity[0..d-1] */
 #define RIDG_FLUX_ROTATION 1 /* 2D solid-body rotation v = (-(y - c_y), x - c_x), c = rot_center */
 #define RIDG_FLUX_AFFINE 2   /* v_i = velocity[i] + sum_j vel_grad[3 i + j] x_j, vel_grad[3 i + i] = 0 */
+
+/* basis families (Sec. 2.1) */
+#define RIDG_BASIS_P 0 /* total degree <= order-1 in space and in space-time */
+#define RIDG_BASIS_Q 1 /* tensor degree <= order-1 per variable (the paper's space); not implemented:
+                          RIDG_E_UNSUPPORTED */
 
 /* arithmetic of the prediction (the correction is always FP64) */
 #define RIDG_FP64 0
@@ -83,10 +90,13 @@ typedef struct ridg_problem {
   int32_t dim;          /* d in {1, 2, 3} */
   int32_t n[3];         /* elements per axis, n[i] >= 3 for i < dim (the 3^d region elements are distinct) */
   int32_t order;        /* M >= 1: basis of total degree M-1; the library implements M <= 5 */
+  int32_t basis;        /* RIDG_BASIS_P (RIDG_BASIS_Q gives RIDG_E_UNSUPPORTED) */
   int32_t flux;         /* RIDG_FLUX_* */
+  int32_t reserved0;    /* must be 0 */
   double velocity[3];   /* CONST: v; AFFINE: constant part */
-  double rot_center[2]; /* ROTATION: centre; must lie on element boundaries (c_x n_x, c_y n_y integers) */
+  double rot_center[2]; /* ROTATION: centre; must lie on element boundaries (c_x / h_x, c_y / h_y integers) */
   double vel_grad[9];   /* AFFINE: row-major dv_i/dx_j, diagonal must be 0 */
+  double length[3];     /* box side lengths L_i > 0 (h_i = L_i / n_i); 0 stands for 1 */
   int32_t precision;    /* RIDG_FP64 or RIDG_FP32_REFINE */
   int32_t refine_steps; /* FP32_REFINE: refinement sweeps 0..3 */
   int32_t solver;       /* RIDG_SOLVER_* */
@@ -103,12 +113,23 @@ typedef struct ridg_info {
   int64_t n_tear_elements;  /* REGION: regions on a dependency cycle solved by tearing one block */
   int64_t n_dense_elements; /* REGION: regions solved by dense LU of the whole region */
   int64_t n_taps;           /* PREFACTORED: non-zero blocks of G (upwind cone) */
-  double flops_predict;     /* per step, prediction: arithmetic of the algorithm actually run (FMA = 2) */
+  /* Algorithmic flops per step (FMA = 2) of the method as the library decomposes it, not instruction
+   * counts: PREFACTORED, the tap products; REGION, per solved block the QQF assembly, the upwind
+   * couplings and an LU-equivalent solve (2/3 theta_T^3 + 2 theta_T^2; the Gauss-Jordan kernels
+   * execute about 1.5x the elimination part); DENSE, LU of the whole region. Correction: the volume
+   * and face terms of Sec. 2.3 term by term (constant velocity: the precombined tap products). */
+  double flops_predict;     /* per step, prediction */
   double flops_correct;     /* per step, correction */
   double bytes_predict;     /* per step, prediction: algorithmic HBM bytes (state in, predictions out) */
   double bytes_correct;     /* per step, correction: state in/out, predictions in */
   double flops_composite;   /* PREFACTORED with RIDG_OPT_COMPOSITE: per step */
   double bytes_composite;   /* PREFACTORED with RIDG_OPT_COMPOSITE: state in/out per step */
+  int32_t basis;            /* RIDG_BASIS_* */
+  int32_t reserved;
+  /* 0 until a step of some dt has been analysed: */
+  double spectral_radius;     /* constant velocity: von Neumann amplification at the dt of the last ridg_step */
+  double static_pivot_growth; /* REGION: growth factor measured for static pivots (layout 5) at the dt of
+                                 the last ridg_step or ridg_get_prediction */
 } ridg_info;
 
 /* Accumulated stage times of ridg_step, from HIP events recorded on the handle's stream. */
@@ -141,8 +162,11 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
 int ridg_set_state(ridg_t* h, const double* q, size_t count, int32_t where);
 
 /* Queue n_steps >= 0 RIDG steps of size dt > 0 on the stream (asynchronous).
- * dt-dependent host tables are rebuilt when dt changes. Returns
- * RIDG_W_UNSTABLE when the CFL number exceeds 1. */
+ * dt-dependent host tables are rebuilt when dt changes (for a constant velocity this includes the
+ * von Neumann analysis of the composed step: eigenvalues of the amplification matrix on a grid of
+ * wavenumbers, 256 points in 1D, 48^2 in 2D, 12^3 in 3D). Returns RIDG_W_UNSTABLE (the steps are
+ * still queued) when that amplification exceeds 1 + 1e-10, or, for an affine velocity, when the CFL
+ * number dt max|v_i| / h_i exceeds 1. */
 int ridg_step(ridg_t* h, int32_t n_steps, double dt);
 
 /* Copy the state out (layout above); synchronises the stream for RIDG_HOST. */
@@ -169,7 +193,12 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
  *     padded to a power of two (DPP reductions), 2 = two regions per packed segment with their
  *     eliminations interleaved, 3 = two rows per lane (half-width segments; each published pivot
  *     row is read once for two rows), 4 = up to three rows per lane in power-of-two segments
- *     (DPP pivot reductions). 2 to 4 are RIDG_FP64 only. Every layout gives bitwise the same results.
+ *     (DPP pivot reductions). 2 to 4 are RIDG_FP64 only and give bitwise the results of 0 and 1.
+ *     5 = the geometry of 4 with static pivots (row c pivots column c, no row exchanges, the next
+ *     pivot row published from registers): FP64 or RIDG_FP32_REFINE. It runs where the host has
+ *     measured elimination in natural order to be stable for the problem's velocity range at the
+ *     step's dt (growth factor <= 64 on every diagonal block form); otherwise the step falls back
+ *     to layout 4 (FP64) or 1 (RIDG_FP32_REFINE). Results agree with the other layouts to rounding.
  *   RIDG_OPT_FUSED (PREFACTORED, meshes whose state and predictions fit in 160 KB of LDS): run all
  *     n_steps of a ridg_step call in one single-workgroup kernel. */
 #define RIDG_OPT_GRAPH 1
@@ -204,6 +233,13 @@ int ridg_synchronize(ridg_t* h);
 
 /* Release the handle (not the workspace). NULL is accepted. */
 int ridg_destroy(ridg_t* h);
+
+/* Host-only von Neumann analysis (Sec. 1 and Sec. 6.1: the stable CFL of RIDG does not shrink with
+ * the order): the largest modulus of an eigenvalue of the constant-velocity step's amplification
+ * matrix I + sum_o K_o e^{i kappa.o} (K_o the composed prediction and correction taps) over a grid
+ * of nk points per axis (2 <= nk <= 4096; at most 2^22 grid points). RIDG_E_INVAL for a
+ * non-constant velocity. */
+int ridg_host_spectral_radius(const ridg_problem* problem, double dt, int32_t nk, double* radius);
 
 /* Host-only inspection of the FP64 precompute (no device needed).
  * Dense region matrix of element e for step dt as assembled by the library

@@ -97,26 +97,3 @@ def l2rel_paper(Q, f_exact, d, n, M, family="P", q=None):
     rest = [j for j in range(len(sidx_p)) if j not in pos]
     err = np.sum((Xp[:, pos] - Q) ** 2) + np.sum(Xp[:, rest] ** 2)
     return float(np.sqrt(err / np.sum(Xp ** 2)))
-
-
-def l2_true(Q, f_exact, d, n, M, q=None, family="P"):
-    """Quadrature L2 norm of (numerical - exact) relative to the exact norm."""
-    n = tuple(n)
-    if q is None:
-        q = M + 6
-    h = np.array([1.0 / k for k in n])
-    sidx = spatial_indices(d, M, family)
-    xi, wt = _elem_points(d, n, h, q)
-    basis = np.array([np.prod([psi(a[j], xi[j]) for j in range(d)], axis=0) for a in sidx])
-    num = 0.0
-    den = 0.0
-    grids = [np.arange(k) for k in n]
-    for e, idx in enumerate(itertools.product(*reversed(grids))):
-        idx = tuple(reversed(idx))
-        xc = np.array([(i + 0.5) * hh for i, hh in zip(idx, h)])
-        X = xc[:, None] + 0.5 * h[:, None] * xi
-        fe = f_exact(X)
-        qh = Q[e] @ basis
-        num += np.sum(wt * (qh - fe) ** 2)
-        den += np.sum(wt * fe ** 2)
-    return float(np.sqrt(num / den))

@@ -345,19 +345,45 @@ def step(prob, Q, dt, n_steps=1):
     return Q
 
 
-def step_sampled(prob, Q, dt, elements):
-    """One step evaluated only at the listed elements (and the predictions they need)."""
-    need = set()
+def _dilate(prob, elements):
+    """The elements within two elements (in every axis) of the given ones: everything one step at
+    them reads (region radius 1, plus 1 for the face neighbours' predictions), periodic."""
+    out = set()
     for e in elements:
-        need.add(e)
         base = prob.multi(e)
-        for i in range(prob.d):
-            for s in (-1, 1):
-                nbr = list(base)
-                nbr[i] += s
-                need.add(prob.linear(tuple(nbr)))
-    W = predict(prob, Q, dt, sorted(need))
-    return correct(prob, Q, W, dt, elements)
+        for o in itertools.product(range(-2, 3), repeat=prob.d):
+            out.add(prob.linear(tuple(b + x for b, x in zip(base, o))))
+    return sorted(out)
+
+
+def step_sampled(prob, Q, dt, elements, n_steps=1):
+    """n_steps full steps evaluated only where they are needed for the listed elements.
+
+    Step j updates only the elements that steps j+1..n_steps read (each step reads the state within
+    two elements of where it is evaluated); the last step updates the listed elements. Returns a
+    dict element -> state after n_steps.
+    """
+    elements = sorted(set(int(e) for e in elements))
+    sets = [elements]
+    for _ in range(n_steps - 1):
+        sets.insert(0, _dilate(prob, sets[0]))
+    Q = np.array(Q, dtype=np.float64, copy=True)
+    out = None
+    for S in sets:
+        need = set()
+        for e in S:
+            need.add(e)
+            base = prob.multi(e)
+            for i in range(prob.d):
+                for s in (-1, 1):
+                    nbr = list(base)
+                    nbr[i] += s
+                    need.add(prob.linear(tuple(nbr)))
+        W = predict(prob, Q, dt, sorted(need))
+        out = correct(prob, Q, W, dt, S)
+        for e, q in out.items():  # entries outside S are stale and never read again
+            Q[e] = q
+    return out
 
 
 def predictions(prob, Q, dt):

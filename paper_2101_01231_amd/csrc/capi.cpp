@@ -27,6 +27,11 @@ int fail(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+}  // namespace
+
+int ridg::set_last_error(int code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
 
 int hip_fail(int err, const char* what) {
   char buf[256];
@@ -179,6 +184,12 @@ struct ridg_handle {
   ridg_info info{};
   PlanTables pt{};
   double pt_dt = -1.0;
+  // static-pivot layout: measured growth of elimination in natural order at pt_dt
+  double sp_growth = 0.0;
+  bool sp_ok = false;
+  // constant velocity: von Neumann amplification of the step at vn_dt
+  double vn_dt = -1.0;
+  double vn_radius = 0.0;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // 3 per timed step
@@ -219,12 +230,12 @@ DevGeom make_geom(const Problem& P) {
 }
 
 double cfl_number(const Problem& P, double dt) {
-  // affine velocity: extremes over the unit box are at its corners
+  // affine velocity: extremes over the box are at its corners
   double best = 0.0;
   for (int c = 0; c < (1 << P.d); ++c) {
     for (int i = 0; i < P.d; ++i) {
       double v = P.vel.a[i];
-      for (int j = 0; j < P.d; ++j) v += P.vel.g[i][j] * ((c >> j) & 1);
+      for (int j = 0; j < P.d; ++j) v += P.vel.g[i][j] * (((c >> j) & 1) ? P.L[j] : 0.0);
       best = std::max(best, std::fabs(v) * dt / P.h[i]);
     }
   }
@@ -307,7 +318,7 @@ const char* ridg_error_string(int code) {
     case RIDG_E_SINGULAR: return "singular region matrix";
     case RIDG_E_NONFINITE: return "non-finite value";
     case RIDG_E_UNSUPPORTED: return "unsupported problem";
-    case RIDG_W_UNSTABLE: return "CFL number above 1";
+    case RIDG_W_UNSTABLE: return "step may be unstable (von Neumann amplification or CFL number above 1)";
     default: return "unknown code";
   }
 }
@@ -472,6 +483,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->cur = 0;
   ridg_info& I = h->info;
   I.abi_version = RIDG_ABI_VERSION;
+  I.basis = RIDG_BASIS_P;
   I.theta = T.ns;
   I.theta_t = T.nt;
   I.solver = P.solver;
@@ -611,11 +623,30 @@ static int ensure_plan_tables(ridg_t* h, double dt) {
   std::memcpy(idx.data(), H.cc_idx.data(), H.cc_idx.size() * 4);  // int32 payload in the last slot
   h->pt.cc_idx = (const int32_t*)push(idx);
   if (buf.size() > h->L.ptab_doubles) return fail(RIDG_E_NOMEM, "plan table layout");
+  h->sp_growth = static_pivot_growth(h->P, H, h->T.nt, dt);
+  h->sp_ok = h->sp_growth <= kStaticPivotMaxGrowth;
+  h->info.static_pivot_growth = h->sp_growth;
   int err = hipMemcpyAsync(base, buf.data(), buf.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipStreamSynchronize(h->stream);
   if (err) return hip_fail(err, "upload of plan tables");
   h->pt_dt = dt;
   return RIDG_OK;
+}
+
+// Warning state of a step of size dt: the von Neumann amplification of the composed step
+// (constant velocity, any solver; analysed once per dt), else the CFL number.
+static int stability_warning(ridg_t* h, double dt) {
+  if (h->P.flux != RIDG_FLUX_CONST) return cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;
+  if (dt != h->vn_dt) {
+    std::string msg;
+    double rho = 0.0;
+    int rc = von_neumann_radius(h->P, h->T, dt, &rho, &msg);
+    if (rc) return fail(rc, msg);
+    h->vn_dt = dt;
+    h->vn_radius = rho;
+    h->info.spectral_radius = rho;
+  }
+  return h->vn_radius > kUnstableRadius ? RIDG_W_UNSTABLE : RIDG_OK;
 }
 
 static int ensure_dt_tables(ridg_t* h, double dt) {
@@ -674,21 +705,26 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
   } else if (P.solver == RIDG_SOLVER_REGION) {
     // cyclic regions (tear and dense kernels) run beside the plan kernel on a forked stream
     const bool side = h->L.n_dense || h->L.n_tear;
-    const int lay = h->opt_layout;
+    // the static-pivot layout runs where elimination in natural order was measured stable for this
+    // dt, else the partial-pivoting layout of the same geometry (FP64) or the packed one (FP32)
+    int lay = h->opt_layout;
+    if (lay == kStaticPivotLayout && !h->sp_ok) lay = P.precision == RIDG_FP64 ? 4 : 1;
     const bool fork = side && h->L.n_items[lay] && h->aux;
     hipStream_t ss = fork ? h->aux : h->stream;
     if (fork) {
       err = hipEventRecord(h->fork_ev, h->stream);
       if (!err) err = hipStreamWaitEvent(h->aux, h->fork_ev, 0);
     }
-    if (!err && h->L.n_items[lay])
-      err = launch_predict_plans(P.d, P.M, lay, P.precision, P.refine, h->geom, dt, Q, h->W, h->pt, h->plans,
-                                 h->items[lay], h->item_plan[lay], h->L.n_items[lay], h->stream);
+    // the few cyclic regions are queued first, so their workgroups are dispatched before the
+    // plan kernel's fill the chip (each is a long dependency chain on a handful of CUs)
     if (!err && h->L.n_tear)
       err = launch_predict_tear(P.d, P.M, h->geom, dt, Q, h->W, h->pt, h->tplans, h->telems, h->L.n_tear, ss);
     if (!err && h->L.n_dense)
       err = launch_predict_dense(P.d, P.M, h->geom, dt, Q, h->W, h->dt, h->dense, h->L.n_dense, h->scratch,
                                  h->L.scratch_elems, ss);
+    if (!err && h->L.n_items[lay])
+      err = launch_predict_plans(P.d, P.M, lay, P.precision, P.refine, h->geom, dt, Q, h->W, h->pt, h->plans,
+                                 h->items[lay], h->item_plan[lay], h->L.n_items[lay], h->stream);
     if (!err && fork) err = hipEventRecord(h->join_ev, h->aux);
     if (!err && fork) err = hipStreamWaitEvent(h->stream, h->join_ev, 0);
   } else {
@@ -793,7 +829,8 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
     return fail(RIDG_E_UNSUPPORTED, "REGION solver supports theta_T <= 64");
   int rc = ensure_dt_tables(h, dt);
   if (rc) return rc;
-  const int warn = cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;
+  const int warn = stability_warning(h, dt);
+  if (warn < 0) return warn;
   if (h->opt_fused && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && fused_fits(h->P.d, h->P.M, h->P.nel)) {
     int err = launch_fused_prefactored(h->P.d, h->P.M, h->geom, dt, h->Q[h->cur], h->Q[1 - h->cur], h->G,
                                        h->host_taps.data(), h->ntaps, h->dt, n_steps, h->stream);
@@ -832,6 +869,14 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
     if (!(dts[i] > 0.0) || !std::isfinite(dts[i])) return fail(RIDG_E_INVAL, "dt must be positive and finite");
     for (int j = 0; j < i; ++j)
       if (handles[j] == h) return fail(RIDG_E_INVAL, "a handle appears twice in the batch");
+  }
+  // a handle whose dt changed gets new operators; earlier batched launches on hip_stream may still
+  // read the old ones, so the upload waits for them
+  bool rebuild = false;
+  for (int i = 0; i < count; ++i) rebuild = rebuild || handles[i]->g_dt != dts[i];
+  if (rebuild) {
+    int err = hipStreamSynchronize((hipStream_t)hip_stream);
+    if (err) return hip_fail(err, "hipStreamSynchronize before the operator upload");
   }
   for (int i = 0; i < count; ++i) {
     int rc = ensure_dt_tables(handles[i], dts[i]);
@@ -930,7 +975,7 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
       break;
     case RIDG_OPT_PLAN_LAYOUT:
       if (h->P.solver != RIDG_SOLVER_REGION && value) return fail(RIDG_E_UNSUPPORTED, "plan layout applies to REGION");
-      if (value >= 2 && h->P.precision != RIDG_FP64)
+      if (value >= 2 && value != kStaticPivotLayout && h->P.precision != RIDG_FP64)
         return fail(RIDG_E_UNSUPPORTED, "plan layouts 2 to 4 are FP64 only");
       h->opt_layout = (int)value;
       break;
@@ -994,8 +1039,17 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   const bool region = h->P.solver == RIDG_SOLVER_REGION;
   const bool pref = h->P.solver == RIDG_SOLVER_PREFACTORED;
   const bool fusable = pref && fused_fits(h->P.d, h->P.M, h->P.nel);
+  {
+    int rc0 = ensure_dt_tables(h, dt);  // the static-pivot check needs this dt's tables
+    if (rc0) return rc0;
+  }
+  std::vector<int> layouts = {0};
+  if (region) {
+    layouts = h->P.precision == RIDG_FP64 ? std::vector<int>{0, 1, 2, 3, 4} : std::vector<int>{0, 1};
+    if (h->sp_ok) layouts.push_back(kStaticPivotLayout);
+  }
   for (int g = 0; g < 2; ++g)
-    for (int l = 0; l < (region ? (h->P.precision == RIDG_FP64 ? kLayouts : 2) : 1); ++l)
+    for (int l : layouts)
       for (int c = 0; c < (pref ? 2 : 1); ++c)
         for (int m = 0; m < (pref ? 2 : 1); ++m) cands.push_back({g, l, 0, c, m});
   if (fusable) cands.push_back({0, 0, 1, 0, 0});
@@ -1102,6 +1156,28 @@ int ridg_host_region_matrix(const ridg_problem* problem, int64_t element, double
   std::vector<double> A;
   assemble_region(P, T, element, dt, offs, &A);
   std::memcpy(a, A.data(), n * n * 8);
+  return RIDG_OK;
+}
+
+int ridg_host_spectral_radius(const ridg_problem* problem, double dt, int32_t nk, double* radius) {
+  Problem P;
+  std::string msg;
+  int rc = resolve_problem(problem, &P, &msg);
+  if (rc) return fail(rc, msg);
+  if (!radius) return fail(RIDG_E_INVAL, "radius is NULL");
+  if (P.flux != RIDG_FLUX_CONST) return fail(RIDG_E_INVAL, "the von Neumann analysis needs a constant velocity");
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be finite and >= 0");
+  if (nk < 2 || nk > 4096 || std::pow((double)nk, P.d) > (double)(1 << 22))
+    return fail(RIDG_E_INVAL, "nk must be in 2..4096 with at most 2^22 grid points");
+  Basis B = make_basis(P.d, P.M);
+  RefTensors T = make_tensors(B);
+  Prefactored pf;
+  rc = build_prefactored(P, T, dt, &pf, &msg);
+  if (rc) return fail(rc, msg);
+  TapOperator dc, kc;
+  build_correction_taps(P, T, dt, &dc);
+  build_composite(P, pf, dc, &kc);
+  *radius = spectral_radius(kc, P.d, nk);
   return RIDG_OK;
 }
 

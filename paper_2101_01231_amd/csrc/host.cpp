@@ -4,7 +4,9 @@
 // prefactored constant-velocity prediction operator.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
+#include <limits>
 #include <map>
 
 #include "ridg_internal.hpp"
@@ -232,6 +234,18 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     *msg = "dim must be 1, 2 or 3";
     return RIDG_E_INVAL;
   }
+  if (p->basis == RIDG_BASIS_Q) {
+    *msg = "the tensor (Q) basis is not implemented";
+    return RIDG_E_UNSUPPORTED;
+  }
+  if (p->basis != RIDG_BASIS_P) {
+    *msg = "unknown basis";
+    return RIDG_E_INVAL;
+  }
+  if (p->reserved0 != 0) {
+    *msg = "reserved0 must be 0";
+    return RIDG_E_INVAL;
+  }
   P.nel = 1;
   for (int i = 0; i < 3; ++i) {
     if (i < P.d) {
@@ -243,11 +257,18 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
         *msg = "n[i] too large";
         return RIDG_E_INVAL;
       }
+      const double L = p->length[i] == 0.0 ? 1.0 : p->length[i];
+      if (!(L > 0.0) || !std::isfinite(L)) {
+        *msg = "length[i] must be positive and finite (0 stands for 1)";
+        return RIDG_E_INVAL;
+      }
       P.n[i] = p->n[i];
-      P.h[i] = 1.0 / p->n[i];
+      P.L[i] = L;
+      P.h[i] = L / p->n[i];
       P.nel *= p->n[i];
     } else {
       P.n[i] = 1;
+      P.L[i] = 1.0;
       P.h[i] = 1.0;
     }
   }
@@ -639,6 +660,76 @@ HostPlanTables build_plan_tables(const Problem& P, const RefTensors& T, double d
   return H;
 }
 
+// Growth of elimination without row exchanges on the diagonal region blocks. V_i0 is affine in
+// the element centre, so its range over the mesh is spanned by the box corners; the grid samples
+// that range (5 points per axis in 1D/2D, 3 in 3D) for every face mask.
+double static_pivot_growth(const Problem& P, const HostPlanTables& H, int nt, double dt) {
+  const int d = P.d;
+  const size_t nn = (size_t)nt * nt;
+  double vmin[3] = {0, 0, 0}, vmax[3] = {0, 0, 0};
+  for (int i = 0; i < d; ++i) {
+    vmin[i] = 1e300;
+    vmax[i] = -1e300;
+    for (int c = 0; c < (1 << d); ++c) {
+      double v = P.vel.a[i];
+      for (int j = 0; j < d; ++j) {
+        const double x = ((c >> j) & 1) ? P.L[j] - 0.5 * P.h[j] : 0.5 * P.h[j];
+        v += P.vel.g[i][j] * x;
+      }
+      v *= dt / P.h[i];
+      vmin[i] = std::min(vmin[i], v);
+      vmax[i] = std::max(vmax[i], v);
+    }
+  }
+  const int per = d == 3 ? 3 : 5;
+  int npts = 1;
+  for (int i = 0; i < d; ++i) npts *= per;
+  double worst = 1.0;
+  std::vector<double> A(nn);
+  for (int mask = 0; mask < (1 << (2 * d)); ++mask) {
+    for (int q = 0; q < npts; ++q) {
+      double V[3] = {0, 0, 0};
+      int r = q;
+      for (int i = 0; i < d; ++i) {
+        const int s = r % per;
+        r /= per;
+        V[i] = vmin[i] + (vmax[i] - vmin[i]) * s / (per - 1);
+      }
+      // only the face masks that occur at this velocity: the outflow face of every axis (s v_i > 0)
+      // takes the block's own trace, so its bit is set
+      bool occurs = true;
+      for (int i = 0; i < d; ++i) {
+        const int bits = (mask >> (2 * i)) & 3;
+        if (V[i] > 0.0 && !(bits & 2)) occurs = false;
+        if (V[i] < 0.0 && !(bits & 1)) occurs = false;
+      }
+      if (!occurs) continue;
+      for (size_t z = 0; z < nn; ++z) A[z] = H.A0[(size_t)mask * nn + z];
+      for (int i = 0; i < d; ++i) {
+        const double* K = &H.K[((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * nn];
+        for (size_t z = 0; z < nn; ++z) A[z] = std::fma(V[i], K[z], A[z]);
+      }
+      double amax = 0.0;
+      for (size_t z = 0; z < nn; ++z) amax = std::max(amax, std::fabs(A[z]));
+      double gmax = amax;
+      for (int c = 0; c < nt; ++c) {
+        const double p = A[(size_t)c * nt + c];
+        if (!(std::fabs(p) > 0.0)) return std::numeric_limits<double>::infinity();
+        for (int rr = c + 1; rr < nt; ++rr) {
+          const double l = A[(size_t)rr * nt + c] / p;
+          if (l == 0.0) continue;
+          for (int j = c + 1; j < nt; ++j) {
+            A[(size_t)rr * nt + j] -= l * A[(size_t)c * nt + j];
+            gmax = std::max(gmax, std::fabs(A[(size_t)rr * nt + j]));
+          }
+        }
+      }
+      worst = std::max(worst, amax > 0.0 ? gmax / amax : std::numeric_limits<double>::infinity());
+    }
+  }
+  return worst;
+}
+
 RegionPlans build_plans(const Problem& P) {
   RegionPlans R;
   R.elem_plan.assign((size_t)P.nel, -1);
@@ -891,6 +982,151 @@ void build_composite(const Problem& P, const Prefactored& G, const TapOperator& 
           for (int c = 0; c < ns; ++c) K[(size_t)r * ns + c] += dv * Gs[(size_t)k * ns + c];
         }
     }
+}
+
+
+// ---------------------------------------------------------------- von Neumann analysis (constant v)
+// Eigenvalues of a complex n x n matrix (row-major): Householder reduction to Hessenberg form, then
+// explicitly shifted QR steps (Givens rotations, Wilkinson shifts) with deflation.
+static void eig_complex(int n, std::vector<std::complex<double>> A, std::vector<std::complex<double>>* ev) {
+  using cd = std::complex<double>;
+  auto at = [&](int r, int c) -> cd& { return A[(size_t)r * n + c]; };
+  for (int k = 0; k + 2 < n; ++k) {  // Householder: zero column k below row k + 1
+    double xn = 0.0;
+    for (int i = k + 1; i < n; ++i) xn += std::norm(at(i, k));
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const cd x0 = at(k + 1, k);
+    const cd ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cd(1.0, 0.0);
+    std::vector<cd> v(n, 0.0);
+    v[k + 1] = x0 + ph * xn;
+    for (int i = k + 2; i < n; ++i) v[i] = at(i, k);
+    double vn = 0.0;
+    for (int i = k + 1; i < n; ++i) vn += std::norm(v[i]);
+    if (vn == 0.0) continue;
+    for (int j = 0; j < n; ++j) {  // A = (I - 2 v v^H / |v|^2) A
+      cd s = 0.0;
+      for (int i = k + 1; i < n; ++i) s += std::conj(v[i]) * at(i, j);
+      s *= 2.0 / vn;
+      for (int i = k + 1; i < n; ++i) at(i, j) -= v[i] * s;
+    }
+    for (int i = 0; i < n; ++i) {  // A = A (I - 2 v v^H / |v|^2)
+      cd s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += at(i, j) * v[j];
+      s *= 2.0 / vn;
+      for (int j = k + 1; j < n; ++j) at(i, j) -= s * std::conj(v[j]);
+    }
+  }
+  ev->clear();
+  int hi = n - 1, iter = 0;
+  std::vector<double> gc(n);
+  std::vector<cd> gs(n);
+  while (hi >= 0) {
+    if (hi == 0) {
+      ev->push_back(at(0, 0));
+      break;
+    }
+    int lo = hi;
+    while (lo > 0) {
+      const double scale = std::abs(at(lo, lo)) + std::abs(at(lo - 1, lo - 1));
+      if (std::abs(at(lo, lo - 1)) <= 1e-15 * (scale > 0.0 ? scale : 1.0)) break;
+      --lo;
+    }
+    if (lo == hi || iter > 300) {  // deflate (or give up on this eigenvalue after many steps)
+      ev->push_back(at(hi, hi));
+      if (hi > 0) at(hi, hi - 1) = 0.0;
+      --hi;
+      iter = 0;
+      continue;
+    }
+    ++iter;
+    const cd a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+    const cd tr = a + d, det = a * d - b * c;
+    const cd disc = std::sqrt(tr * tr / 4.0 - det);
+    cd mu = (std::abs(tr / 2.0 + disc - d) < std::abs(tr / 2.0 - disc - d)) ? tr / 2.0 + disc : tr / 2.0 - disc;
+    if (iter % 11 == 10) mu = d + std::abs(at(hi, hi - 1));  // exceptional shift
+    for (int k = lo; k <= hi; ++k) at(k, k) -= mu;
+    for (int k = lo; k < hi; ++k) {  // QR of the active block by Givens rotations
+      const cd x = at(k, k), y = at(k + 1, k);
+      const double r = std::sqrt(std::norm(x) + std::norm(y));
+      double cc = 1.0;
+      cd ss = 0.0;
+      if (r > 0.0) {
+        if (std::abs(x) == 0.0) {
+          cc = 0.0;
+          ss = std::conj(y) / std::abs(y);
+        } else {
+          cc = std::abs(x) / r;
+          ss = (x / std::abs(x)) * std::conj(y) / r;
+        }
+      }
+      gc[k] = cc;
+      gs[k] = ss;
+      for (int j = k; j < n; ++j) {
+        const cd p = at(k, j), q = at(k + 1, j);
+        at(k, j) = cc * p + ss * q;
+        at(k + 1, j) = -std::conj(ss) * p + cc * q;
+      }
+    }
+    for (int k = lo; k < hi; ++k) {  // R Q
+      const double cc = gc[k];
+      const cd ss = gs[k];
+      const int rmax = std::min(k + 2, hi);
+      for (int i = 0; i <= rmax; ++i) {
+        const cd p = at(i, k), q = at(i, k + 1);
+        at(i, k) = p * cc + q * std::conj(ss);
+        at(i, k + 1) = -p * ss + q * cc;
+      }
+    }
+    for (int k = lo; k <= hi; ++k) at(k, k) += mu;
+  }
+}
+
+double spectral_radius(const TapOperator& K, int d, int nk) {
+  using cd = std::complex<double>;
+  const int ns = K.rows;
+  int npts = 1;
+  for (int i = 0; i < d; ++i) npts *= nk;
+  double worst = 0.0;
+  std::vector<cd> G((size_t)ns * ns);
+  std::vector<cd> ev;
+  const double two_pi = 6.283185307179586476925;
+  for (int q = 0; q < npts; ++q) {
+    double kap[3] = {0, 0, 0};
+    int r = q;
+    for (int i = 0; i < d; ++i) {
+      kap[i] = two_pi * (r % nk) / nk;
+      r /= nk;
+    }
+    for (int z = 0; z < ns * ns; ++z) G[z] = 0.0;
+    for (int z = 0; z < ns; ++z) G[(size_t)z * ns + z] = 1.0;  // the identity of Q' = Q + ...
+    for (size_t t = 0; t < K.offs.size(); ++t) {
+      double ph = 0.0;
+      for (int i = 0; i < d; ++i) ph += kap[i] * K.offs[t][i];
+      const cd e(std::cos(ph), std::sin(ph));
+      const double* A = &K.A[t * (size_t)ns * ns];
+      for (int z = 0; z < ns * ns; ++z) G[z] += e * A[z];
+    }
+    eig_complex(ns, G, &ev);
+    for (const cd& x : ev) worst = std::max(worst, std::abs(x));
+  }
+  return worst;
+}
+
+int von_neumann_radius(const Problem& P, const RefTensors& T, double dt, double* rho, std::string* msg) {
+  if (P.flux != RIDG_FLUX_CONST) {
+    *msg = "the von Neumann analysis needs a constant velocity";
+    return RIDG_E_INVAL;
+  }
+  Prefactored pf;
+  int rc = build_prefactored(P, T, dt, &pf, msg);
+  if (rc) return rc;
+  TapOperator dc, kc;
+  build_correction_taps(P, T, dt, &dc);
+  build_composite(P, pf, dc, &kc);
+  const int nk = P.d == 1 ? 256 : (P.d == 2 ? 48 : 12);
+  *rho = spectral_radius(kc, P.d, nk);
+  return RIDG_OK;
 }
 
 }  // namespace ridg

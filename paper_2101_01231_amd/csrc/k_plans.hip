@@ -102,7 +102,7 @@ struct IpwL {
   static int run(int layout) {
     if (layout == 2) return 2 * PlanCfg<D, M, false>::S;
     if (layout == 3) return PlanCfg2R<D, M>::S;
-    if (layout == 4) return PlanCfgDpp<D, M>::S;
+    if (layout == 4 || layout == kStaticPivotLayout) return PlanCfgDpp<D, M>::S;
     return layout ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S;
   }
 };
@@ -131,6 +131,8 @@ struct PlansL {
                  const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
+    if (layout == kStaticPivotLayout)
+      return launch_plans_sp(D, M, precision, refine, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);
     if (layout >= 2) {  // FP64-only layouts, each compiled in its own unit
       if (precision != RIDG_FP64) return (int)hipErrorInvalidValue;
       if (layout == 2) return launch_plans2(D, M, g, dt, Q, W, t, plans, items, item_plan, n_items, stream);

@@ -10,171 +10,207 @@ namespace ridg {
 // right-hand sides, giving W_r = alpha_r + B_r x; the tear block's own equations then form one
 // theta_T x theta_T system for x, and W_centre = alpha_c + B_c x. This solves exactly the region
 // system of eq. (pred_full_system) restricted to the centre's ancestors.
-template <int NT, int LB, bool POW2, int R>
-__device__ inline void seg_solve_multi(double (&a)[NT], double (&rhs)[R], int k, bool idle,
-                                       const int (&addr)[LB > 0 ? LB : 1], double* piv, double* x) {
+//
+// One workgroup of kTearWaves wavefronts per region. Every wavefront assembles and eliminates the
+// same block matrices (identical arithmetic, hence identical pivots) and carries its own slice of
+// the right-hand-side columns [alpha | B], so the registers hold theta_T + ceil((1 + theta_T) /
+// kTearWaves) values per row and every index into them is static. A block's columns depend only
+// on the same columns of its upwind sources, so the wavefronts run independently until the tear
+// equation, which needs every column.
+constexpr int kTearWaves = 4;
+
+template <int NT>
+struct TearCfg {
+  static constexpr int R = 1 + NT;                            // right-hand sides: alpha and B
+  static constexpr int RW = (R + kTearWaves - 1) / kTearWaves;  // columns per wavefront
+  static constexpr int SEGW = seg_width(NT);                  // rows in a power-of-two lane segment
+  static constexpr int LB = log2_ceil(SEGW);
+};
+
+// Gauss-Jordan elimination with partial pivoting (the pivot rule of seg_solve) of [A | rhs] with
+// RW right-hand sides; row k of A in lane k. Columns r < ncols of the solution go to
+// x[step * ldx + r] (LDS).
+template <int NT, int SEGW, int RW>
+__device__ inline void seg_solve_gj_rhs(double (&a)[NT], double (&rhs)[RW], int k, bool idle, double* piv,
+                                        double* x, int ldx, int ncols) {
+  constexpr int LB = log2_ceil(SEGW);
   constexpr unsigned LMASK = (1u << LB) - 1u;
+  constexpr int PS = NT + RW + 1;  // published row: a[c+1..NT-1], rhs, 1/pivot
   bool used = idle;
   int mystep = -1;
   double myinv = 0.0;
-#pragma unroll
-  for (int c = 0; c < NT; ++c) {
+  static_for<0, NT>([&](auto C) {
+    constexpr int c = decltype(C)::value;
+    double* pv = piv + (c & 1) * PS;
     unsigned key = 0u;
     if (!used) key = (__float_as_uint((float)fabs(a[c])) & ~LMASK) | (LMASK - (unsigned)k);
-    if constexpr (POW2)
-      key = seg_max_pow2<(NT > 1 ? NT : 1)>(key);
-    else
-      key = seg_max_rot<NT, LB>(key, addr);
+    key = seg_max_pow2<SEGW>(key);
     const int p = (int)(LMASK - (key & LMASK));
-    if (k == p && !idle) {
+    const bool is_piv = (k == p) && !idle;
+    if (is_piv) {
       myinv = recip(a[c]);
 #pragma unroll
-      for (int j = c + 1; j < NT; ++j) piv[j] = a[j];
+      for (int j = c + 1; j < NT; ++j) pv[j] = a[j];
 #pragma unroll
-      for (int j = 0; j < R; ++j) piv[NT + j] = rhs[j];
-      piv[NT + R] = myinv;
+      for (int r = 0; r < RW; ++r) pv[NT + r] = rhs[r];
+      pv[NT + RW] = myinv;
       used = true;
       mystep = c;
     }
     wave_sync();
-    if (!used) {
-      const double l = a[c] * piv[NT + R];
+    if (!is_piv && !idle) {
+      const double l = a[c] * pv[NT + RW];
 #pragma unroll
-      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, piv[j], a[j]);
+      for (int j = c + 1; j < NT; ++j) a[j] = fma(-l, pv[j], a[j]);
 #pragma unroll
-      for (int j = 0; j < R; ++j) rhs[j] = fma(-l, piv[NT + j], rhs[j]);
+      for (int r = 0; r < RW; ++r) rhs[r] = fma(-l, pv[NT + r], rhs[r]);
     }
-    wave_sync();
-  }
-#pragma unroll 1
-  for (int c = NT - 1; c >= 0; --c) {
-    if (mystep == c)
+  });
+  if (mystep >= 0) {
 #pragma unroll
-      for (int j = 0; j < R; ++j) x[c * R + j] = rhs[j] * myinv;
-    wave_sync();
-    if (mystep >= 0 && mystep < c) {
-      double ac = a[0];
-#pragma unroll
-      for (int q = 1; q < NT; ++q) ac = (q == c) ? a[q] : ac;
-#pragma unroll
-      for (int j = 0; j < R; ++j) rhs[j] = fma(-ac, x[c * R + j], rhs[j]);
-    }
+    for (int r = 0; r < RW; ++r)
+      if (r < ncols) x[mystep * ldx + r] = rhs[r] * myinv;
   }
   wave_sync();
 }
 
 template <int D, int M>
-__global__ __launch_bounds__(64) void predict_tear_kernel(DevGeom g, double dt, const double* __restrict__ Q,
-                                                          double* __restrict__ W, PlanTables t,
-                                                          const PlanRec* __restrict__ plans,
-                                                          const int32_t* __restrict__ elems, int64_t n_elems) {
-  using C = PlanCfg<D, M>;
-  if constexpr (C::NT <= 64) {
-  constexpr int NT = C::NT, NB = C::NB, LB = C::LB, R = 1 + NT;
-  __shared__ double s_w[NB][NT][R];  // [alpha | B] of every eliminated block
-  __shared__ double s_piv[2 * (NT + R + 1)];
-  __shared__ double s_x[NT];
-  const int64_t item = blockIdx.x;
-  if (item >= n_elems) return;
-  const int lane = threadIdx.x & 63;
-  const bool idle = lane >= NT;
-  const int k = idle ? 0 : lane;
-  int addr[LB > 0 ? LB : 1];
+__global__ __launch_bounds__(64 * kTearWaves) void predict_tear_kernel(DevGeom g, double dt,
+                                                                       const double* __restrict__ Q,
+                                                                       double* __restrict__ W, PlanTables t,
+                                                                       const PlanRec* __restrict__ plans,
+                                                                       const int32_t* __restrict__ elems,
+                                                                       int64_t n_elems) {
+  constexpr int NT = n_spacetime(D, M);
+  if constexpr (NT <= 64) {
+    using C = TearCfg<NT>;
+    constexpr int NB = PlanCfg<D, M>::NB, R = C::R, RW = C::RW, SEGW = C::SEGW;
+    __shared__ double s_w[NB][NT][R];  // [alpha | B] of every eliminated block
+    __shared__ double s_piv[kTearWaves][2 * (NT + RW + 1)];
+    __shared__ double s_x[NT];
+    const int64_t item = blockIdx.x;
+    if (item >= n_elems) return;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const bool idle = lane >= NT;
+    const int k = idle ? 0 : lane;
+    const int j0 = wave * RW;                             // first right-hand-side column of this wavefront
+    const int ncols = R - j0 < RW ? (R - j0 > 0 ? R - j0 : 0) : RW;
+    const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+    const int32_t e = elems[item];
+    int base[3];
+    elem_idx(g, e, base);
+    const PlanRec* pr = plans + item;
+    const int nb = pr->nb;
+    const int centre = pr->pad[1];
+    const int ccl = t.cc_idx[k];
+    const double ccv = t.cc_val[k];
+    double* piv = &s_piv[wave][0];
+    // assembled row k of the diagonal block of plan block b, its causal source, and V0
+    // (plan records are read in place: a copied record indexed by face would live in scratch memory)
+    auto assemble = [&](int b, double (&a)[NT], double& src0, double (&V0)[D]) {
+      const PlanBlock* blk = &pr->blk[b];
+      int mask = 0;
 #pragma unroll
-  for (int r = 0; r < LB; ++r) addr[r] = 4 * (idle ? lane : (k + (1 << r)) % NT);
-  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int32_t e = elems[item];
-  int base[3];
-  elem_idx(g, e, base);
-  const PlanRec* pr = plans + item;
-  const int nb = pr->nb;
-  const int centre = pr->pad[1];
-  const int ccl = t.cc_idx[k];
-  const double ccv = t.cc_val[k];
-  // blocks in elimination order; block 0 (the tear block) last
-  for (int bb = 1; bb <= nb; ++bb) {
-    const int b = bb < nb ? bb : 0;
-    const PlanBlock blk = pr->blk[b];
-    int mask = 0;
+      for (int i = 0; i < D; ++i)
+        mask |= ((blk->src[2 * i] == kOwn ? 1 : 0) | (blk->src[2 * i + 1] == kOwn ? 2 : 0)) << (2 * i);
+      const int gi[3] = {wrap(base[0] + blk->off[0], g.n0), wrap(base[1] + blk->off[1], g.n1),
+                         wrap(base[2] + blk->off[2], g.n2)};
+      const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
 #pragma unroll
-    for (int i = 0; i < D; ++i)
-      mask |= ((blk.src[2 * i] == kOwn ? 1 : 0) | (blk.src[2 * i + 1] == kOwn ? 2 : 0)) << (2 * i);
-    const int gi[3] = {wrap(base[0] + blk.off[0], g.n0), wrap(base[1] + blk.off[1], g.n1),
-                       wrap(base[2] + blk.off[2], g.n2)};
-    const int64_t ge = (int64_t)gi[0] + (int64_t)g.n0 * ((int64_t)gi[1] + (int64_t)g.n1 * gi[2]);
-    double V0[D];
+      for (int i = 0; i < D; ++i) {
+        double v = g.a[i];
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double v = g.a[i];
-#pragma unroll
-      for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
-      V0[i] = v * dt / geom_h(g, i);
-    }
-    double a[NT];
-    {
+        for (int j = 0; j < D; ++j) v += g.g[i][j] * ((gi[j] + 0.5) * geom_h(g, j));
+        V0[i] = v * dt / geom_h(g, i);
+      }
       const double* a0 = t.A0 + ((size_t)mask * NT + k) * NT;
 #pragma unroll
       for (int l = 0; l < NT; ++l) a[l] = a0[l];
-    }
 #pragma unroll 1
-    for (int i = 0; i < D; ++i) {
-      const double vi = sel<D>(V0, i);
-      const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT + k) * NT;
+      for (int i = 0; i < D; ++i) {
+        const double vi = sel<D>(V0, i);
+        const double* kk = t.K + (((size_t)i * 4 + ((mask >> (2 * i)) & 3)) * NT + k) * NT;
 #pragma unroll
-      for (int l = 0; l < NT; ++l) a[l] = fma(vi, kk[l], a[l]);
-    }
-    double rhs[R];
+        for (int l = 0; l < NT; ++l) a[l] = fma(vi, kk[l], a[l]);
+      }
+      src0 = ccv * Q[(int64_t)ccl * nel + ge];
+    };
+    // eliminated blocks in plan order (block 0, the tear block, comes last)
+    for (int b = 1; b < nb; ++b) {
+      const uint8_t* bsrc = pr->blk[b].src;
+      double a[NT], V0[D], src0;
+      assemble(b, a, src0, V0);
+      double rhs[RW];
 #pragma unroll
-    for (int j = 0; j < R; ++j) rhs[j] = 0.0;
-    rhs[0] = ccv * Q[(int64_t)ccl * nel + ge];
+      for (int r = 0; r < RW; ++r) rhs[r] = (j0 + r == 0) ? src0 : 0.0;
 #pragma unroll 1
-    for (int i = 0; i < D; ++i) {
-      const double vi = sel<D>(V0, i);
+      for (int i = 0; i < D; ++i) {
+        const double vi = sel<D>(V0, i);
 #pragma unroll 1
-      for (int sd = 0; sd < 2; ++sd) {
-        const int src = blk.src[2 * i + sd];
-        if (src == kOwn) continue;
-        const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + k) * NT;
-        const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + k) * NT;
-        if (src == 0) {  // coupling to the tear unknowns: -A_{b,0} x
+        for (int sd = 0; sd < 2; ++sd) {
+          const int src = bsrc[2 * i + sd];
+          if (src == kOwn) continue;
+          const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + k) * NT;
+          const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + k) * NT;
+          if (src == 0) {  // coupling to the tear unknowns: column 1 + l of B gets -A_{b,0}[k][l]
 #pragma unroll
-          for (int l = 0; l < NT; ++l) rhs[1 + l] -= fma(vi, f0[l], fc[l]);
-        } else if (b != 0) {  // -A_{b,s} (alpha_s + B_s x)
+            for (int r = 0; r < RW; ++r) {
+              const int l = j0 + r - 1;
+              if (l >= 0 && l < NT) rhs[r] -= fma(vi, f0[l], fc[l]);
+            }
+          } else {  // -A_{b,s} (alpha_s + B_s x), this wavefront's columns
+            const double* ws = &s_w[src][0][0] + j0;
 #pragma unroll 1
-          for (int l = 0; l < NT; ++l) {
-            const double cl = fma(vi, f0[l], fc[l]);
+            for (int l = 0; l < NT; ++l) {
+              const double cl = fma(vi, f0[l], fc[l]);
 #pragma unroll
-            for (int j = 0; j < R; ++j) rhs[j] = fma(-cl, s_w[src][l][j], rhs[j]);
+              for (int r = 0; r < RW; ++r)
+                if (r < ncols) rhs[r] = fma(-cl, ws[l * R + r], rhs[r]);
+            }
           }
-        } else {  // tear equation: A_00 x + A_{0,s} (alpha_s + B_s x) = b_0
+        }
+      }
+      seg_solve_gj_rhs<NT, SEGW, RW>(a, rhs, k, idle, piv, &s_w[b][0][0] + j0, R, ncols);
+    }
+    __syncthreads();  // every column of every eliminated block is in LDS
+    if (wave != 0) return;
+    {  // tear equation: A_00 x + sum_s A_{0,s} (alpha_s + B_s x) = b_0
+      double a[NT], V0[D], r0;
+      assemble(0, a, r0, V0);
+      const uint8_t* bsrc = pr->blk[0].src;
+#pragma unroll 1
+      for (int i = 0; i < D; ++i) {
+        const double vi = sel<D>(V0, i);
+#pragma unroll 1
+        for (int sd = 0; sd < 2; ++sd) {
+          const int src = bsrc[2 * i + sd];
+          if (src == kOwn) continue;
+          const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + k) * NT;
+          const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + k) * NT;
 #pragma unroll 1
           for (int l = 0; l < NT; ++l) {
             const double cl = fma(vi, f0[l], fc[l]);
-            rhs[0] = fma(-cl, s_w[src][l][0], rhs[0]);
+            r0 = fma(-cl, s_w[src][l][0], r0);
 #pragma unroll
             for (int j = 0; j < NT; ++j) a[j] = fma(cl, s_w[src][l][1 + j], a[j]);
           }
         }
       }
+      double rr[1] = {r0};
+      seg_solve_gj_rhs<NT, SEGW, 1>(a, rr, k, idle, piv, s_x, 1, 1);
     }
-    if (b != 0) {
-      seg_solve_multi<NT, LB, C::POW2, R>(a, rhs, k, idle, addr, s_piv, &s_w[b][0][0]);
-    } else {
-      double r0 = rhs[0];
-      seg_solve<NT, LB, C::POW2>(a, r0, k, idle, addr, s_piv, s_x);
-    }
-  }
-  if (!idle) {
-    double w;
-    if (centre == 0) {
-      w = s_x[k];
-    } else {
-      w = s_w[centre][k][0];
+    if (!idle) {
+      double w;
+      if (centre == 0) {
+        w = s_x[k];
+      } else {
+        w = s_w[centre][k][0];
 #pragma unroll
-      for (int j = 0; j < NT; ++j) w = fma(s_w[centre][k][1 + j], s_x[j], w);
+        for (int j = 0; j < NT; ++j) w = fma(s_w[centre][k][1 + j], s_x[j], w);
+      }
+      W[(int64_t)k * nel + e] = w;
     }
-    W[(int64_t)k * nel + e] = w;
-  }
   }  // theta_T <= 64
 }
 
@@ -309,8 +345,8 @@ struct TearL {
                  const int32_t* elems, int64_t n_elems, void* stream) {
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
     if (n_elems == 0) return 0;
-    hipLaunchKernelGGL((predict_tear_kernel<D, M>), dim3((unsigned)n_elems), dim3(64), 0, (hipStream_t)stream, g, dt,
-                       Q, W, t, plans, elems, n_elems);
+    hipLaunchKernelGGL((predict_tear_kernel<D, M>), dim3((unsigned)n_elems), dim3(64 * kTearWaves), 0,
+                       (hipStream_t)stream, g, dt, Q, W, t, plans, elems, n_elems);
     return (int)hipGetLastError();
   }
 };

@@ -88,12 +88,18 @@ __device__ inline int face_side(const DevGeom& g, const int idx[3], int i, int s
   return (s * c0 - spread >= -tol) ? 0 : 1;
 }
 
-// element i of a small register array without dynamic indexing (a select chain)
+// element i of a small register array without dynamic indexing (a select chain). Each element
+// passes through an empty asm operand (no instruction): otherwise the compiler may fold the
+// selects of loads into one indexed load and keep the array in scratch memory.
 template <int D>
 __device__ inline double sel(const double (&v)[D], int i) {
   double r = v[0];
 #pragma unroll
-  for (int j = 1; j < D; ++j) r = (i == j) ? v[j] : r;
+  for (int j = 1; j < D; ++j) {
+    double vj = v[j];
+    asm("" : "+v"(vj));
+    r = (i == j) ? vj : r;
+  }
   return r;
 }
 
@@ -164,6 +170,12 @@ __device__ inline double recip(double x) {
   r = fma(r, e, r);
   e = fma(-x, r, 1.0);
   return fma(r, e, r);
+}
+
+// 1/x in FP32: hardware reciprocal estimate and one Newton step (FP32 eliminations only).
+__device__ inline float recipf(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
 // Compile-time loop: f(std::integral_constant<int, I>) for I = B..E-1.
@@ -300,7 +312,7 @@ using PlanCfgDpp = PlanCfgNR<D, M, (n_spacetime(D, M) + seg_width_nr(n_spacetime
 // Gauss-Jordan with partial pivoting as seg_solve, each lane holding RPL rows: one read of the
 // published pivot row updates all of them (1/RPL of the LDS traffic of one row per lane).
 template <class C>
-__device__ inline void seg_solve_nr(double (&a)[C::RPL][C::NT], double (&rhs)[C::RPL], int k,
+__device__ __forceinline__ void seg_solve_nr(double (&a)[C::RPL][C::NT], double (&rhs)[C::RPL], int k,
                                     const bool (&idle)[C::RPL], const int (&addr)[C::LB > 0 ? C::LB : 1], double* piv,
                                     double* x) {
   constexpr int NT = C::NT, RPL = C::RPL, SEGW = C::SEGW;

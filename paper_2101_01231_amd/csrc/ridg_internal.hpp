@@ -65,12 +65,16 @@ struct Problem {
   int M = 0;
   int flux = 0;
   Affine vel;
+  double L[3] = {1, 1, 1};  // box side lengths
   double h[3] = {1, 1, 1};
   int precision = 0;
   int refine = 0;
   int solver = 0;  // resolved
   int64_t nel = 0;
 };
+
+// Record msg as the calling thread's ridg_last_error() and return code.
+int set_last_error(int code, const std::string& msg);
 
 // Validate and resolve a public problem description. Returns RIDG_OK or an error (msg set).
 int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg);
@@ -147,6 +151,12 @@ void build_correction_taps(const Problem& P, const RefTensors& T, double dt, Tap
 // Prediction and correction composed: Q'_e = Q_e + sum_o K_o Q_{e+o}, K_o = sum_{t+s=o} D_t G_s.
 void build_composite(const Problem& P, const Prefactored& G, const TapOperator& Dc, TapOperator* out);
 constexpr int kMaxTapUpdate = 125;  // composite offsets in {-2..2}^3
+// Von Neumann analysis of the constant-velocity step Q' = Q + sum_o K_o Q_{.+o}: the largest
+// modulus of an eigenvalue of I + sum_o K_o e^{i kappa.o} over a grid of nk points per axis.
+double spectral_radius(const TapOperator& K, int d, int nk);
+// The same for the problem's composed step at dt (grid: 256 points in 1D, 48^2 in 2D, 12^3 in 3D).
+int von_neumann_radius(const Problem& P, const RefTensors& T, double dt, double* rho, std::string* msg);
+constexpr double kUnstableRadius = 1.0 + 1e-10;
 // A operator [tap][rows][cols] rearranged as MFMA A fragments: [row tile][tap][chunk][lane] holding
 // A_t[16 tile + lane % 16][4 chunk + lane / 16], zero outside rows x cols (16x16x4 layout).
 std::vector<double> mfma_fragments(const double* A, int ntaps, int rows, int cols);
@@ -264,8 +274,10 @@ int launch_predict_plans(int d, int M, int layout, int precision, int refine, co
                          const double* Q, double* W, const PlanTables& t, const PlanRec* plans,
                          const int32_t* items, const int32_t* item_plan, int64_t n_items, void* stream);
 // plan-kernel segment layouts: 0 packed, 1 padded to a power of two, 2 two regions per packed
-// segment, 3 two rows per lane, 4 several rows per lane in power-of-two (DPP) segments
-constexpr int kLayouts = 5;
+// segment, 3 two rows per lane, 4 several rows per lane in power-of-two (DPP) segments, 5 the
+// layout-4 geometry with static pivots (row c pivots column c)
+constexpr int kLayouts = 6;
+constexpr int kStaticPivotLayout = 5;
 int items_per_wave(int d, int M, int layout);
 // the FP64-only layouts (separate translation units)
 int launch_plans2(int d, int M, const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
@@ -276,6 +288,15 @@ int launch_plans_2rows(int d, int M, const DevGeom& g, double dt, const double* 
 int launch_plans_dpp(int d, int M, const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
                      const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
                      void* stream);  // work-list padding multiple (regions a wavefront takes at once)
+// static pivots (layout 5): FP64 or RIDG_FP32_REFINE with `refine` FP64-residual sweeps
+int launch_plans_sp(int d, int M, int precision, int refine, const DevGeom& g, double dt, const double* Q, double* W,
+                    const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
+                    int64_t n_items, void* stream);
+// Largest growth factor max|U| / max|A| of elimination without row exchanges over the diagonal
+// region blocks A0[mask] + sum_i V_i K_i[mask_i] of the tables, for V on a grid spanning the
+// problem's range of V_i0 = v_i(element centre) dt / h_i (inf where a pivot vanishes).
+double static_pivot_growth(const Problem& P, const HostPlanTables& H, int nt, double dt);
+constexpr double kStaticPivotMaxGrowth = 64.0;
 // Whole run of n_steps on one workgroup (mesh state resident in LDS), constant velocity;
 // returns hipErrorInvalidValue when the mesh does not fit.
 int fused_fits(int d, int M, int64_t nel);

@@ -25,6 +25,8 @@ RIDG_E_UNSUPPORTED = -6
 RIDG_W_UNSTABLE = 1
 
 FLUX_CONST, FLUX_ROTATION, FLUX_AFFINE = 0, 1, 2
+BASIS_P, BASIS_Q = 0, 1
+ABI_VERSION = 2
 FP64, FP32_REFINE = 0, 1
 SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
@@ -34,7 +36,8 @@ EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
     "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_set_option",
     "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_synchronize", "ridg_destroy",
-    "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_error_string", "ridg_last_error",
+    "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_host_spectral_radius",
+    "ridg_error_string", "ridg_last_error",
 ]
 
 
@@ -43,10 +46,13 @@ class RidgProblem(ctypes.Structure):
         ("dim", ctypes.c_int32),
         ("n", ctypes.c_int32 * 3),
         ("order", ctypes.c_int32),
+        ("basis", ctypes.c_int32),
         ("flux", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
         ("velocity", ctypes.c_double * 3),
         ("rot_center", ctypes.c_double * 2),
         ("vel_grad", ctypes.c_double * 9),
+        ("length", ctypes.c_double * 3),
         ("precision", ctypes.c_int32),
         ("refine_steps", ctypes.c_int32),
         ("solver", ctypes.c_int32),
@@ -71,6 +77,10 @@ class RidgInfo(ctypes.Structure):
         ("bytes_correct", ctypes.c_double),
         ("flops_composite", ctypes.c_double),
         ("bytes_composite", ctypes.c_double),
+        ("basis", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("spectral_radius", ctypes.c_double),
+        ("static_pivot_growth", ctypes.c_double),
     ]
 
 
@@ -118,6 +128,7 @@ def lib():
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
         L.ridg_host_prediction_operator.argtypes = [P, dbl, vp, sz]
+        L.ridg_host_spectral_radius.argtypes = [P, dbl, i32, ctypes.POINTER(dbl)]
         L.ridg_error_string.restype = ctypes.c_char_p
         L.ridg_error_string.argtypes = [ctypes.c_int]
         L.ridg_last_error.restype = ctypes.c_char_p
@@ -135,14 +146,19 @@ def _check(rc):
 
 
 def make_problem(dim, n, order, velocity=None, flux=FLUX_CONST, rot_center=(0.5, 0.5), vel_grad=None,
-                 precision=FP64, refine_steps=0, solver=SOLVER_AUTO):
+                 precision=FP64, refine_steps=0, solver=SOLVER_AUTO, basis=BASIS_P, length=None):
     p = RidgProblem()
     p.dim = dim
     n = tuple(n) if hasattr(n, "__len__") else (n,) * dim
     for i in range(3):
         p.n[i] = n[i] if i < len(n) else 1
     p.order = order
+    p.basis = basis
     p.flux = flux
+    p.reserved0 = 0
+    L = tuple(length or ())
+    for i in range(3):
+        p.length[i] = float(L[i]) if i < len(L) else 0.0
     v = tuple(velocity or ())
     for i in range(3):
         p.velocity[i] = float(v[i]) if i < len(v) else 0.0
@@ -183,6 +199,13 @@ def host_prediction_operator(problem, dt):
     return G
 
 
+def host_spectral_radius(problem, dt, nk=64):
+    """Von Neumann amplification of the constant-velocity step (host precompute, no device)."""
+    out = ctypes.c_double()
+    _check(lib().ridg_host_spectral_radius(ctypes.byref(problem), float(dt), int(nk), ctypes.byref(out)))
+    return out.value
+
+
 def step_batch(sims, dts, n_steps, stream):
     """Advance several PREFACTORED simulations in shared launches on `stream` (a torch stream)."""
     n = len(sims)
@@ -214,6 +237,12 @@ class Simulation:
         self.theta = self.info.theta
         self.theta_t = self.info.theta_t
         self.n_el = self.info.n_elements
+
+    def get_info(self):
+        """Sizes, cost model and the per-dt analyses of the handle (ridg_info)."""
+        info = RidgInfo()
+        _check(lib().ridg_get_info(self.handle, ctypes.byref(info)))
+        return info
 
     def close(self):
         if getattr(self, "handle", None):

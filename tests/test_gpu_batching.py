@@ -15,6 +15,11 @@ def _rot(n, M, **kw):
     return ridg.make_problem(2, (n, n), M, flux=ridg.FLUX_ROTATION, rot_center=(0.5, 0.5), **kw)
 
 
+def _max_elem_rel(a, b):
+    """Largest per-element error relative to the state's largest element norm."""
+    return float(np.max(np.linalg.norm(a - b, axis=1)) / np.max(np.linalg.norm(b, axis=1)))
+
+
 def _run(problem, q0, dt, steps, options=(), chunks=None):
     sim = ridg.Simulation(problem)
     for opt, val in options:
@@ -64,6 +69,16 @@ def test_plan_layouts_agree(case):
         assert np.array_equal(a, b), lay
     ref = S.step(ref_prob, q0, dt, 3)
     assert np.linalg.norm(a - ref) / np.linalg.norm(ref) <= 1e-12
+    # static pivots: a different elimination, the same solution to rounding
+    sim = ridg.Simulation(p)
+    sim.set_option(ridg.OPT_PLAN_LAYOUT, 5)
+    sim.set_state(q0)
+    sim.step(3, dt)
+    sp = sim.get_state()
+    assert sim.get_info().static_pivot_growth <= 64.0  # static pivots ran (no fallback)
+    sim.close()
+    assert np.linalg.norm(sp - ref) / np.linalg.norm(ref) <= 1e-12
+    assert _max_elem_rel(sp, ref) <= 1e-11
 
 
 def test_two_region_layout_rejected_for_fp32():
@@ -75,7 +90,8 @@ def test_two_region_layout_rejected_for_fp32():
     with pytest.raises(ridg.RidgError):
         sim.set_option(ridg.OPT_PLAN_LAYOUT, 3)
     with pytest.raises(ridg.RidgError):
-        sim.set_option(ridg.OPT_PLAN_LAYOUT, 5)
+        sim.set_option(ridg.OPT_PLAN_LAYOUT, 6)
+    sim.set_option(ridg.OPT_PLAN_LAYOUT, 5)  # static pivots take FP32 with refinement
     sim.close()
 
 
@@ -122,7 +138,9 @@ def test_autotune_keeps_state_and_results(kind):
 
 
 @pytest.mark.parametrize("d,n,M,v", [(3, (6, 5, 4), 3, (1.0, 1.0, 1.0)), (2, (24, 20), 4, (1.0, 0.5)),
-                                     (1, (40,), 5, (-0.8,)), (2, (9, 8), 2, (0.0, -0.6))])
+                                     (1, (40,), 5, (-0.8,)), (2, (9, 8), 2, (0.0, -0.6)),
+                                     (3, (4, 3, 5), 4, (0.6, -0.8, 0.3)), (3, (3, 4, 3), 5, (-0.5, 0.7, 0.9)),
+                                     (2, (17, 19), 5, (0.3, 0.9))])
 def test_composite_and_tap_correction_match_oracle(d, n, M, v):
     """Constant velocity: the tap-form correction (default) and the composite stencil against the oracle."""
     p = ridg.make_problem(d, n, M, velocity=v)

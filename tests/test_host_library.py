@@ -44,6 +44,8 @@ CASES = [
     dict(dim=2, n=(6, 6), order=2, flux=ridg.FLUX_ROTATION, rot_center=(0.5, 0.5)),
     dict(dim=3, n=(3, 4, 3), order=2, velocity=(1.0, 1.0, 1.0)),
     dict(dim=3, n=(3, 3, 3), order=3, velocity=(0.4, -0.7, 0.2)),
+    dict(dim=3, n=(4, 3, 3), order=4, velocity=(0.6, -0.8, 0.3)),
+    dict(dim=3, n=(3, 3, 4), order=5, velocity=(-0.5, 0.7, 0.9)),
 ]
 
 
@@ -87,6 +89,10 @@ BAD = [
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), refine_steps=9), ridg.RIDG_E_INVAL),
     (dict(dim=1, n=((1 << 20) + 1,), order=2, velocity=(1,)), ridg.RIDG_E_INVAL),  # axis above 2^20
     (dict(dim=3, n=(2048, 2048, 1024), order=1, velocity=(1, 1, 1)), ridg.RIDG_E_INVAL),  # 2^32 elements
+    (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), basis=ridg.BASIS_Q), ridg.RIDG_E_UNSUPPORTED),
+    (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), basis=7), ridg.RIDG_E_INVAL),
+    (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), length=(1.0, -2.0)), ridg.RIDG_E_INVAL),
+    (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), length=(float("inf"), 1.0)), ridg.RIDG_E_INVAL),
 ]
 
 
@@ -127,3 +133,49 @@ def test_rotation_plans_cover_every_element():
     """The region solver sends every element either to an upwind plan or to the dense path."""
     p = ridg.make_problem(2, (16, 16), 4, flux=ridg.FLUX_ROTATION, solver=ridg.SOLVER_REGION)
     assert ridg.workspace_bytes(p) > 0
+
+
+def test_box_lengths_match_oracle():
+    """length[]: the region matrices of a non-unit box (h_i = L_i / n_i) against the oracle's."""
+    for case in (dict(dim=2, n=(6, 5), order=3, velocity=(1.0, -0.5), length=(2.0, 0.5)),
+                 dict(dim=2, n=(8, 6), order=3, flux=ridg.FLUX_ROTATION, rot_center=(1.0, 0.75), length=(2.0, 1.5)),
+                 dict(dim=3, n=(3, 4, 3), order=2, velocity=(0.3, 1.0, -0.4), length=(1.0, 3.0, 0.25))):
+        p = ridg.make_problem(**case)
+        d = case["dim"]
+        vel = ("const", case["velocity"]) if "velocity" in case else ("rotation", case["rot_center"])
+        prob = S.Problem(d=d, n=case["n"], M=case["order"], velocity=vel, length=case["length"])
+        dt = 0.3 * min(prob.h)
+        for e in sorted({0, prob.n_el // 2, prob.n_el - 1}):
+            A = ridg.host_region_matrix(p, e, dt)
+            Ao, _, _, _ = S.region_system(prob, e, np.zeros((prob.n_el, prob.theta)), dt)
+            np.testing.assert_allclose(A, Ao, atol=1e-13 * max(1.0, np.abs(Ao).max()))
+
+
+@pytest.mark.parametrize("d,M,v,nu", [(1, 3, (1.0,), 0.5), (1, 3, (1.0,), 1.3), (1, 4, (-0.7,), 0.6),
+                                      (2, 2, (1.0, 0.5), 0.5), (2, 3, (0.6, -1.0), 0.7)])
+def test_host_spectral_radius_matches_oracle(d, M, v, nu):
+    """The library's von Neumann amplification (composed exact-tensor taps, its own complex
+    eigenvalue solver) against the oracle's (impulse responses of its quadrature-assembled step,
+    LAPACK eigenvalues) on the same wavenumber grid."""
+    from oracle.stability import spectral_radius, stencil
+    n = (5,) * d
+    p = ridg.make_problem(d, n, M, velocity=v)
+    dt = nu * (1.0 / 5) / max(abs(x) for x in v)
+    nk = 16
+    got = ridg.host_spectral_radius(p, dt, nk)
+    ref = spectral_radius(stencil(d, M, v, nu), d, nk)
+    assert abs(got - ref) <= 1e-10 * ref, (got, ref)
+
+
+def test_unstable_warning_threshold_follows_von_neumann():
+    """RIDG_W_UNSTABLE is the von Neumann limit, not CFL 1: 2D order 4 with v = (1, 0.5) is stable at
+    CFL 0.5 and unstable at CFL 0.8 (the oracle's stability pins find the limit near 0.64), on the
+    48^2 wavenumber grid the library uses; 1D order 2 stays stable above CFL 1 (limit near 1.11)."""
+    p = ridg.make_problem(2, (16, 16), 4, velocity=(1.0, 0.5))
+    h = 1.0 / 16
+    assert ridg.host_spectral_radius(p, 0.5 * h, 48) <= 1 + 1e-10
+    assert ridg.host_spectral_radius(p, 0.8 * h, 48) > 1 + 1e-10
+    p1 = ridg.make_problem(1, (16,), 2, velocity=(1.0,))
+    assert ridg.host_spectral_radius(p1, 1.05 * h, 256) <= 1 + 1e-10
+    with pytest.raises(ridg.RidgError):
+        ridg.host_spectral_radius(ridg.make_problem(2, (16, 16), 3, flux=ridg.FLUX_ROTATION), 0.01, 16)

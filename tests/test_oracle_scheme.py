@@ -386,3 +386,64 @@ def test_rotation_bump_converges():
         errs.append(np.linalg.norm(Q1 - ex) / np.linalg.norm(ex))
     order = math.log(errs[0] / errs[1]) / math.log(2)
     assert order > M - 0.7, (errs, order)
+
+
+# ------------------------------------------------------------ the sampled step behind full-size parity
+@pytest.mark.parametrize("n_steps", [1, 2])
+def test_step_sampled_equals_full_step_rotation(n_steps):
+    """step_sampled (the reference of every full-size GPU parity test) gives exactly what the whole
+    mesh's step gives on corner, edge, interior and circulation-point elements (8^2, order 4)."""
+    prob = S.Problem(d=2, n=(8, 8), M=4, velocity=("rotation", (0.5, 0.5)))
+    rng = np.random.default_rng(41)
+    Q = rng.standard_normal((prob.n_el, prob.theta)) * 0.5 ** np.array([sum(a) for a in prob.sidx])
+    dt = 0.5 / (8 * 0.5)
+    el = [prob.linear(ij) for ij in [(0, 0), (7, 7), (0, 7), (7, 0), (0, 3), (3, 0), (3, 4), (4, 4), (3, 3), (5, 6)]]
+    full = S.step(prob, Q, dt, n_steps)
+    got = S.step_sampled(prob, Q, dt, el, n_steps)
+    assert sorted(got) == sorted(el)
+    for e in el:
+        np.testing.assert_allclose(got[e], full[e], rtol=0, atol=1e-14 * np.abs(full).max())
+
+
+def test_step_sampled_equals_full_step_3d():
+    prob = S.Problem(d=3, n=(5, 4, 4), M=3, velocity=("const", (1.0, -0.5, 0.75)))
+    rng = np.random.default_rng(42)
+    Q = rng.standard_normal((prob.n_el, prob.theta))
+    dt = 0.4 / (5 * 1.0)
+    el = [0, prob.n_el - 1, prob.linear((2, 1, 3)), prob.linear((4, 0, 2))]
+    for n_steps in (1, 2):
+        full = S.step(prob, Q, dt, n_steps)
+        got = S.step_sampled(prob, Q, dt, el, n_steps)
+        for e in el:
+            np.testing.assert_allclose(got[e], full[e], rtol=0, atol=1e-14 * np.abs(full).max())
+
+
+# ------------------------------------------------------------ eq. (l2relerror)
+def _local_mode(d, n, M, axis, c):
+    """1 + c psi_M(xi_axis): a constant plus one next-degree mode on every element (local coords)."""
+    h = 1.0 / n
+
+    def f(X):
+        x = X[axis]
+        xc = (np.floor(x / h) + 0.5) * h
+        return 1.0 + c * basis.psi(M, 2.0 * (x - xc) / h)
+    return f
+
+
+@pytest.mark.parametrize("d,M", [(1, 2), (1, 4), (2, 3)])
+def test_l2rel_paper_closed_forms(d, M):
+    """eq. (l2relerror) on data with known coefficients: the constant mode is 1 and the only
+    next-degree mode has coefficient c, so the exact projection onto the basis (order M) is the
+    constant and the error is the truncation term alone, sqrt(c^2 / (1 + c^2)); an error delta in
+    one retained mode adds delta^2 to the numerator; data inside the basis gives 0."""
+    n = (6,) * d
+    c, delta = 0.3, 0.05
+    f = _local_mode(d, 6, M, 0, c)
+    Q = np.zeros((6 ** d, len(basis.spatial_indices(d, M))))
+    Q[:, 0] = 1.0
+    assert abs(l2rel_paper(Q, f, d, n, M) - math.sqrt(c * c / (1 + c * c))) < 1e-13
+    Q[:, 1] += delta
+    assert abs(l2rel_paper(Q, f, d, n, M) - math.sqrt((c * c + delta * delta) / (1 + c * c))) < 1e-13
+    # data inside the basis: a global polynomial of degree M - 1 and its projection
+    g = lambda X: 0.5 + X[0] ** (M - 1) - 0.25 * X[-1]
+    assert l2rel_paper(project(g, d, n, M), g, d, n, M) < 1e-13
