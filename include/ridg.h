@@ -228,6 +228,20 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
  * advances exactly as ridg_step would advance it alone with RIDG_OPT_COMPOSITE off. */
 int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, int32_t n_steps, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under stream capture, serving loops with a
+ * fixed memory plan): n_steps >= 0 steps of size dt > 0 of a constant-velocity FP64 problem
+ * (RIDG_SOLVER_AUTO or RIDG_SOLVER_PREFACTORED), as ridg_create + ridg_set_state + ridg_step +
+ * ridg_get_state would advance it with the default options, without a handle or a workspace.
+ * q_in, q_out: device arrays in the state layout above (count = n_elements * theta; q_out may equal
+ * q_in), owned by the caller. Queued on hip_stream (asynchronous; the host-side FP64 operator
+ * precompute runs in the call and is cached per problem and dt). Intermediates (two states, the
+ * predictions, the operators) live in a static per-device scratch array of 64 MiB: problems that
+ * need more return RIDG_E_NOMEM before any device work. No device memory is allocated or freed.
+ * Every call on one device shares that scratch: calls that overlap on a device (several host
+ * threads or streams) race and must be serialised by the caller. */
+int ridg_advance_static(const ridg_problem* problem, const double* q_in, double* q_out, size_t count,
+                        int32_t n_steps, double dt, void* hip_stream);
+
 /* Wait for all queued work of the handle. */
 int ridg_synchronize(ridg_t* h);
 

@@ -35,7 +35,7 @@ OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE, OPT_MFMA = 1, 2, 3, 4, 5
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
     "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_set_option",
-    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_synchronize", "ridg_destroy",
+    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_advance_static", "ridg_synchronize", "ridg_destroy",
     "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_host_spectral_radius",
     "ridg_error_string", "ridg_last_error",
 ]
@@ -124,6 +124,7 @@ def lib():
         L.ridg_get_option.argtypes = [vp, i32, ctypes.POINTER(i64)]
         L.ridg_autotune.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
         L.ridg_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), i32, vp]
+        L.ridg_advance_static.argtypes = [P, vp, vp, sz, i32, dbl, vp]
         L.ridg_synchronize.argtypes = [vp]
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
@@ -204,6 +205,16 @@ def host_spectral_radius(problem, dt, nk=64):
     out = ctypes.c_double()
     _check(lib().ridg_host_spectral_radius(ctypes.byref(problem), float(dt), int(nk), ctypes.byref(out)))
     return out.value
+
+
+def advance_static(problem, q_in, q_out, n_steps, dt, stream=None):
+    """ridg_advance_static on torch device tensors (state layout of set/get); no device allocation."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(q_in.device)
+    return _check(lib().ridg_advance_static(ctypes.byref(problem), ctypes.c_void_p(q_in.data_ptr()),
+                                            ctypes.c_void_p(q_out.data_ptr()), q_in.numel(), int(n_steps),
+                                            float(dt), ctypes.c_void_p(stream.cuda_stream)))
 
 
 def step_batch(sims, dts, n_steps, stream):
