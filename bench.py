@@ -193,9 +193,10 @@ def make_problem(wl, precision, solver, refine):
                              precision=prec, solver=sol, refine_steps=refine)
 
 
-def cpu_baseline(wl, target_s):
+def cpu_baseline(wl, target_s, threads_limit=None, _prob=None, _label=None):
     """The oracle (plain FP64, quadrature assembly, dense LAPACK region solves) on a square
-    patch of elements of the same workload; rate scaled to ST-DOF-updates/s."""
+    patch of elements of the same workload; rate scaled to ST-DOF-updates/s. threads_limit caps the
+    BLAS pool (1: the single-thread leg)."""
     import oracle.scheme as S
     try:
         from threadpoolctl import threadpool_info
@@ -203,6 +204,12 @@ def cpu_baseline(wl, target_s):
     except Exception:
         threads = 1
     prob = S.Problem(d=wl.d, n=wl.n, M=wl.M, velocity=wl.velocity)
+    if threads_limit:
+        from threadpoolctl import threadpool_limits
+        with threadpool_limits(limits=threads_limit):
+            return cpu_baseline(wl, target_s, threads_limit=None, _prob=prob, _label=f"{threads_limit} BLAS thread(s)")
+    if _prob is not None:
+        prob = _prob
     side = 4
     elapsed = 0.0
     done = 0
@@ -235,13 +242,17 @@ def cpu_baseline(wl, target_s):
     rate = done * prob.theta_t / elapsed
     used = max(1, int(math.ceil(cpu / elapsed - 0.05))) if elapsed > 0 else 1  # threads busy on average
     return {"value": rate, "unit": "ST-DOF-updates/s", "cores": used, "threads_available": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "blas_threads": _label or "all",
             "sample": f"{reps} step(s) (prediction of the sampled elements and their face neighbours + correction) "
                       f"on a {side}^{wl.d} patch of the {'x'.join(map(str, wl.n))} mesh, {elapsed:.1f} s"}
 
 
-def run_path(wl, precision, solver, refine, steps, warmup, label):
-    """Time one configuration; returns the measurements and the final state."""
+def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_steps=1000):
+    """Time one configuration; returns the measurements and the final state.
+
+    Throughput: `trials` runs of `steps` steps, each one ridg_step call from the same initial state
+    with the autotuned options; the median trial is reported with the spread. Latency: `lat_steps`
+    single steps (one launch sequence each), HIP events around every step."""
     import torch
     from paper_2101_01231_amd import ridg
 
@@ -269,11 +280,12 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     if warmup:
         sim.step(warmup, wl.dt)
     sim.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    nlat = max(lat_steps, steps)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(nlat)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(nlat)]
     sim.enable_timing(True)
     torch.cuda.synchronize()
-    for s in range(steps):
+    for s in range(nlat):
         starts[s].record(stream)
         sim.step(1, wl.dt)
         ends[s].record(stream)
@@ -281,23 +293,28 @@ def run_path(wl, precision, solver, refine, steps, warmup, label):
     tim = sim.get_timing()
     sim.enable_timing(False)
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
-    # throughput pass, from the initial state again: the autotuned options, all timed steps in one call
+    # throughput: the autotuned options, all timed steps in one call, from the initial state each trial
     sim.set_option(ridg.OPT_GRAPH, tuned["graph"])
     sim.set_option(ridg.OPT_FUSED, tuned["fused"])
-    sim.set_state(q0_dev)
-    if warmup:
-        sim.step(warmup, wl.dt)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    sim.step(steps, wl.dt)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    q = sim.get_state()
+    walls = []
+    q = None
+    for _ in range(trials):
+        sim.set_state(q0_dev)
+        if warmup:
+            sim.step(warmup, wl.dt)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps, wl.dt)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        if q is None:
+            q = sim.get_state()
     sim.close()
+    wall = float(np.median(walls))
     pred_ms = tim.predict_ms / max(tim.steps, 1)
     corr_ms = tim.correct_ms / max(tim.steps, 1)
-    return dict(info=info, wall=wall, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q, opts=opts,
+    return dict(info=info, wall=wall, walls=walls, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q, opts=opts,
                 value=info.n_elements * info.theta_t * steps / wall)
 
 
@@ -340,8 +357,9 @@ def serving(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "serving-mix", "requests": len(reqs), "arrival_rate_per_s": 20 * args.time_scale,
                    "mem_budget_gb": args.mem_gb},
-        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"]},
-        "wall_s": st["wall_s"], "busy_s": st["busy_s"], "mean_active": st["mean_active"],
+        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"], "samples": st["latency_samples"]},
+        "wall_s": st["wall_s"], "busy_s": st["busy_s"], "busy_fraction": st["busy_s"] / st["wall_s"],
+        "mean_active": st["mean_active"],
         "st_dof_updates_per_s_wall": st["st_dof_updates_per_s_wall"], "rejected": len(st["rejected"]),
     }
     print(json.dumps(out), flush=True)
@@ -356,6 +374,8 @@ def main():
     ap.add_argument("--precision", default="best", choices=["best", "fp64", "fp32"])
     ap.add_argument("--refine", type=int, default=1)
     ap.add_argument("--solver", default="auto")
+    ap.add_argument("--trials", type=int, default=5, help="timed trials of --steps steps (median reported)")
+    ap.add_argument("--latency-steps", type=int, default=1000, help="single steps timed for p50/p99")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -383,7 +403,8 @@ def main():
     has_fp32 = wl.velocity[0] != "const" or args.solver == "region"
     want = ["fp64", "fp32"] if (args.precision == "best" and has_fp32) else \
         (["fp64"] if args.precision == "best" else [args.precision])
-    runs = {p: run_path(wl, p, args.solver, args.refine, args.steps, args.warmup, p) for p in want}
+    runs = {p: run_path(wl, p, args.solver, args.refine, args.steps, args.warmup, p, args.trials, args.latency_steps)
+            for p in want}
     T = (args.warmup + args.steps) * wl.dt
     ex = None
     if not args.no_accuracy:
@@ -455,7 +476,9 @@ def main():
                    "refine_steps": args.refine if best == "fp32" else 0},
         "spatial_dof_updates_per_s": info.n_elements * info.theta * args.steps / R["wall"],
         "latency_ms": {"p50": float(np.percentile(R["lat"], 50)), "p99": float(np.percentile(R["lat"], 99)),
-                       "max": float(R["lat"].max())},
+                       "max": float(R["lat"].max()), "samples": int(R["lat"].size)},
+        "trials": {"count": len(R["walls"]), "ms_per_step": [w * 1e3 / args.steps for w in R["walls"]],
+                   "median_ms_per_step": R["wall"] * 1e3 / args.steps},
         "roofline": roofline,
         "paths": {p: {"value": r["value"], "ms_per_step": r["wall"] * 1e3 / args.steps,
                       "p99_ms": float(np.percentile(r["lat"], 99)), "prediction_ms": r["pred_ms"],
@@ -470,6 +493,9 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        print("[bench] timing the CPU oracle on one BLAS thread", file=sys.stderr, flush=True)
+        one = cpu_baseline(wl, args.cpu_seconds, threads_limit=1)
+        out["cpu_baseline"]["single_thread"] = {k: one[k] for k in ("value", "unit", "cores", "sample")}
     print(json.dumps(out), flush=True)
 
 

@@ -221,7 +221,9 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
 
 /* Serving: advance `count` handles by n_steps steps, handle i with step size dts[i], in shared
  * launches queued on hip_stream (the handles' own streams are not used; order calls on them with
- * ridg_synchronize or by using that same stream). Handles with the same dimension, order and
+ * ridg_synchronize or by using that same stream). When a handle's dt differs from the one its
+ * earlier batched launches used, its operators are rebuilt after hip_stream has been synchronised
+ * (those launches may still read them); the first batched call of a handle does not synchronise. Handles with the same dimension, order and
  * RIDG_OPT_MFMA setting share one prediction and one correction launch per step (up to 16 per
  * launch; the matrix-core or the vector kernels, as the option selects). Every handle must use
  * RIDG_SOLVER_PREFACTORED (constant velocity) on the same device and appear once; each state

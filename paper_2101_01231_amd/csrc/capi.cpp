@@ -190,6 +190,8 @@ struct ridg_handle {
   // constant velocity: von Neumann amplification of the step at vn_dt
   double vn_dt = -1.0;
   double vn_radius = 0.0;
+  // dt of the operators that ridg_step_batch launches have read (-1: none yet)
+  double batch_dt = -1.0;
   // stage timing
   bool timing = false;
   std::vector<hipEvent_t> events;  // 3 per timed step
@@ -871,9 +873,9 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
       if (handles[j] == h) return fail(RIDG_E_INVAL, "a handle appears twice in the batch");
   }
   // a handle whose dt changed gets new operators; earlier batched launches on hip_stream may still
-  // read the old ones, so the upload waits for them
+  // read the old ones, so the upload waits for them (not needed for operators no batch has read)
   bool rebuild = false;
-  for (int i = 0; i < count; ++i) rebuild = rebuild || handles[i]->g_dt != dts[i];
+  for (int i = 0; i < count; ++i) rebuild = rebuild || (handles[i]->g_dt != dts[i] && handles[i]->batch_dt >= 0.0);
   if (rebuild) {
     int err = hipStreamSynchronize((hipStream_t)hip_stream);
     if (err) return hip_fail(err, "hipStreamSynchronize before the operator upload");
@@ -960,6 +962,7 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
     }
     for (int i = 0; i < count; ++i) handles[i]->cur ^= 1;
   }
+  for (int i = 0; i < count; ++i) handles[i]->batch_dt = dts[i];
   return RIDG_OK;
 }
 

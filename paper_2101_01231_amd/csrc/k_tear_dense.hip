@@ -161,7 +161,7 @@ __global__ __launch_bounds__(64 * kTearWaves) void predict_tear_kernel(DevGeom g
             }
           } else {  // -A_{b,s} (alpha_s + B_s x), this wavefront's columns
             const double* ws = &s_w[src][0][0] + j0;
-#pragma unroll 1
+#pragma unroll
             for (int l = 0; l < NT; ++l) {
               const double cl = fma(vi, f0[l], fc[l]);
 #pragma unroll
@@ -188,7 +188,7 @@ __global__ __launch_bounds__(64 * kTearWaves) void predict_tear_kernel(DevGeom g
           if (src == kOwn) continue;
           const double* f0 = t.Fn0 + (((size_t)i * 2 + sd) * NT + k) * NT;
           const double* fc = t.FnC + (((size_t)i * 2 + sd) * NT + k) * NT;
-#pragma unroll 1
+#pragma unroll
           for (int l = 0; l < NT; ++l) {
             const double cl = fma(vi, f0[l], fc[l]);
             r0 = fma(-cl, s_w[src][l][0], r0);

@@ -10,11 +10,15 @@ order, each with its own number of steps and step size) arrive over time. The se
     (`ridg_step_batch`: one prediction and one correction launch per (dimension, order) family);
     requests with large space-time bases (theta_T >= MFMA_MIN_THETA_T) run on the FP64 matrix
     cores, the others on the vector kernels (the same choice is made when a request runs alone);
-  * retires finished requests (state copied back, workspace freed) and admits waiting ones.
+  * keeps the device fed: tick k + 1 is queued before tick k has finished (at most two ticks in
+    flight); a request leaves the active set when its last step has been queued, and is retired
+    (state copied back, workspace freed) once that tick's event has completed. Uploads of admitted
+    requests go on a separate stream, so admission does not wait for queued ticks.
 
-Per-step latency is measured with HIP events on the server's stream (a step becomes eligible when
-its tick starts and completes when the tick's launches finish). A request that cannot be served
-(invalid, or larger than the whole budget) is rejected alone; the others continue.
+Per-step latency is measured with HIP events on the server's stream, from when a request's step
+becomes eligible (the end of its previous step, or the start of its first tick) to the end of the
+tick that computes it. Busy time is the sum of the ticks' execution intervals. A request that cannot
+be served (invalid, or larger than the whole budget) is rejected alone; the others continue.
 """
 
 import time
@@ -77,7 +81,8 @@ class Server:
 
         self.torch = torch
         self.device = torch.device(device)
-        self.stream = torch.cuda.Stream(self.device)  # default priority
+        self.stream = torch.cuda.Stream(self.device)  # batched steps (default priority)
+        self.upload = torch.cuda.Stream(self.device)  # handles' own stream: uploads and read-backs
         self.budget = int(mem_budget_bytes)
         self.max_active = max_active
         self.used = 0
@@ -89,29 +94,52 @@ class Server:
             raise ridg.RidgError(ridg.RIDG_E_NOMEM, f"request {req.id} needs {need} bytes, budget {self.budget}")
         if self.used + need > self.budget:
             return None
-        sim = ridg.Simulation(prob, device=self.device, stream=self.stream)
+        sim = ridg.Simulation(prob, device=self.device, stream=self.upload)
         req.configure(sim)
-        sim.set_state(req.initial_state())
+        sim.set_state(req.initial_state())  # synchronous on the upload stream only
         self.used += need
-        return dict(req=req, sim=sim, bytes=need, done=0, admitted=time.perf_counter())
+        return dict(req=req, sim=sim, bytes=need, issued=0, last_end=None)
 
     def run(self, requests, time_scale=1.0, keep_results=True):
         """Serve the requests (arrival times in seconds, divided by time_scale); returns stats."""
         torch = self.torch
         pending = deque(sorted(requests, key=lambda r: r.arrival))
         waiting = deque()
-        active = []
+        active, retiring = [], []  # retiring: (slot, end event of its last tick)
+        inflight = deque()  # ticks queued, not yet accounted: (start, end, [(slot, eligible event)])
         results, rejected = {}, {}
         lat_ms, tick_ms, active_counts = [], [], []
         st_updates = 0
         t0 = time.perf_counter()
-        busy = 0.0
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
-        while pending or waiting or active:
+
+        def account(tick):
+            ev0, ev1, members = tick
+            ev1.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            tick_ms.append(ms)
+            for slot, eligible in members:
+                lat_ms.append(eligible.elapsed_time(ev1) if eligible is not None else ms)
+
+        def retire_ready(block=False):
+            nonlocal retiring
+            keep = []
+            for slot, ev in retiring:
+                if block or ev.query():
+                    ev.synchronize()
+                    q = slot["sim"].get_state()
+                    if keep_results:
+                        results[slot["req"].id] = q
+                    slot["sim"].close()
+                    self.used -= slot["bytes"]
+                else:
+                    keep.append((slot, ev))
+            retiring = keep
+
+        while pending or waiting or active or retiring or inflight:
             now = (time.perf_counter() - t0) * time_scale
             while pending and pending[0].arrival <= now:
                 waiting.append(pending.popleft())
+            retire_ready()
             while waiting and len(active) < self.max_active:
                 try:
                     slot = self._admit(waiting[0])
@@ -122,39 +150,44 @@ class Server:
                     break
                 waiting.popleft()
                 active.append(slot)
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, (pending[0].arrival - now) / time_scale))
+            if active:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev1 = torch.cuda.Event(enable_timing=True)
+                ev0.record(self.stream)
+                ridg.step_batch([a["sim"] for a in active], [a["req"].dt for a in active], 1, self.stream)
+                ev1.record(self.stream)
+                inflight.append((ev0, ev1, [(a, a["last_end"]) for a in active]))
+                active_counts.append(len(active))
+                still = []
+                for a in active:
+                    a["issued"] += 1
+                    a["last_end"] = ev1
+                    st_updates += a["req"].st_dofs_per_step
+                    if a["issued"] >= a["req"].steps:
+                        retiring.append((a, ev1))
+                    else:
+                        still.append(a)
+                active = still
+                while len(inflight) > 2:  # at most two ticks queued ahead of the host
+                    account(inflight.popleft())
                 continue
-            sims = [a["sim"] for a in active]
-            dts = [a["req"].dt for a in active]
-            tb = time.perf_counter()
-            ev0.record(self.stream)
-            ridg.step_batch(sims, dts, 1, self.stream)
-            ev1.record(self.stream)
-            ev1.synchronize()
-            busy += time.perf_counter() - tb
-            ms = ev0.elapsed_time(ev1)
-            tick_ms.append(ms)
-            active_counts.append(len(active))
-            lat_ms.extend([ms] * len(active))
-            still = []
-            for a in active:
-                a["done"] += 1
-                st_updates += a["req"].st_dofs_per_step
-                if a["done"] >= a["req"].steps:
-                    q = a["sim"].get_state()
-                    if keep_results:
-                        results[a["req"].id] = q
-                    a["sim"].close()
-                    self.used -= a["bytes"]
-                else:
-                    still.append(a)
-            active = still
+            # nothing to launch: drain what is queued, then wait for retirements or arrivals
+            while inflight:
+                account(inflight.popleft())
+            if retiring:
+                retire_ready(block=not (pending or waiting))
+                continue
+            if pending and not waiting:
+                time.sleep(max(0.0, (pending[0].arrival - now) / time_scale))
+            elif waiting and not retiring:
+                # nothing active and the head of the queue does not fit: it never will
+                rejected[waiting.popleft().id] = "does not fit the memory budget"
         wall = time.perf_counter() - t0
+        busy = sum(tick_ms) * 1e-3
         lat = np.array(lat_ms) if lat_ms else np.zeros(1)
         return dict(results=results, rejected=rejected, wall_s=wall, busy_s=busy, ticks=len(tick_ms),
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    latency_samples=int(lat.size),
                     mean_active=float(np.mean(active_counts)) if active_counts else 0.0,
                     st_dof_updates=st_updates,
                     st_dof_updates_per_s_busy=st_updates / busy if busy else 0.0,
