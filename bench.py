@@ -45,7 +45,7 @@ KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
                 "fused_prefactored_kernel": ["k_prefactored.hip"], "correct_kernel": ["k_correct.hip"],
                 "predict_tear_kernel": ["k_tear_dense.hip"], "predict_dense_kernel": ["k_tear_dense.hip"],
                 "batch_predict_kernel": ["k_batch.hip"], "batch_correct_kernel": ["k_batch.hip"],
-                "tap_mfma_kernel": ["k_mfma.hip"]}
+                "tap_mfma_kernel": ["k_mfma.hip"], "brick_step_kernel": ["k_brick.hip"]}
 RECORD_TAG = "traffic-record: "
 
 
@@ -67,6 +67,8 @@ def dominant_kernel(info, opts, precision):
     from paper_2101_01231_amd import ridg
     d, M = _dim_order(info)
     if info.solver == ridg.SOLVER_PREFACTORED:
+        if opts.get("brick") or precision == "fp32":
+            return f"ridg::brick_step_kernel<{M}, {'float' if precision == 'fp32' else 'double'}>"
         if opts.get("mfma"):
             cols = info.theta
             rows = info.theta if opts.get("composite") else info.theta_t
@@ -268,7 +270,7 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
     tuned = {"graph": sim.get_option(ridg.OPT_GRAPH), "fused": sim.get_option(ridg.OPT_FUSED)}
     opts = {"plan_layout": sim.get_option(ridg.OPT_PLAN_LAYOUT), "composite": sim.get_option(ridg.OPT_COMPOSITE),
-            "mfma": sim.get_option(ridg.OPT_MFMA), **tuned}
+            "mfma": sim.get_option(ridg.OPT_MFMA), "brick": sim.get_option(ridg.OPT_BRICK), **tuned}
     print(f"[bench] {label}: {wl.name} n={wl.n} M={wl.M} solver={info.solver} plans={info.n_plans} "
           f"tear={info.n_tear_elements} dense={info.n_dense_elements} warmup={warmup} steps={steps} opts={opts}",
           file=sys.stderr, flush=True)
@@ -400,7 +402,10 @@ def main():
     if args.workload == "copy":
         return copy_reference(args)
     wl = workload(args.workload)
-    has_fp32 = wl.velocity[0] != "const" or args.solver == "region"
+    # reduced precision: FP32 region solves (variable velocity, or the REGION solver), or the 3D brick
+    # kernel's FP32 matrix-core predictions (constant velocity on a brick-divisible mesh)
+    brickable = wl.d == 3 and wl.M in (2, 3) and wl.n[0] % 16 == 0 and wl.n[1] % 4 == 0 and wl.n[2] % 4 == 0
+    has_fp32 = wl.velocity[0] != "const" or args.solver == "region" or (brickable and args.solver == "auto")
     want = ["fp64", "fp32"] if (args.precision == "best" and has_fp32) else \
         (["fp64"] if args.precision == "best" else [args.precision])
     runs = {p: run_path(wl, p, args.solver, args.refine, args.steps, args.warmup, p, args.trials, args.latency_steps)
@@ -435,13 +440,18 @@ def main():
         roofline["traffic_detail"] = tr
     if info.solver == ridg.SOLVER_PREFACTORED:
         comp = R["opts"]["composite"]
-        nbytes = info.bytes_composite if comp else info.bytes_predict
-        nflops = info.flops_composite if comp else info.flops_predict
+        brick = bool(R["opts"].get("brick")) or best == "fp32"
+        nbytes = info.bytes_composite if (comp or brick) else info.bytes_predict
+        nflops = (info.flops_predict + info.flops_correct) if brick else (info.flops_composite if comp else info.flops_predict)
         bw = nbytes / (R["pred_ms"] * 1e-3) / 1e9
         tf = nflops / (R["pred_ms"] * 1e-3) / 1e12
         kern = "composite prediction+correction stencil" if comp else "prediction (prefactored G)"
         mfma = bool(R["opts"].get("mfma"))
-        if mfma:
+        if brick:
+            kern = ("fused brick step (FP32 matrix-core predictions, FP64 correction)" if best == "fp32" else
+                    "fused brick step (FP64 matrix-core predictions, FP64 correction)")
+            mfma = best != "fp32"  # the FP32 path is priced against HBM (its products run at 2x the FP64 roof)
+        elif mfma:
             kern += " on FP64 MFMA"
         # the roof that binds: whichever fraction is larger
         if mfma and tf / FP64_MFMA_PEAK_TFLOPS > bw / HBM_PEAK_GBS:
@@ -467,7 +477,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "fp64" else "f32+f64-refine",
+        "dtype": "f64" if best == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": wl.name, "n": list(wl.n), "order": wl.M, "theta_t": info.theta_t,
                    "velocity": list(map(str, wl.velocity[1])), "dt": wl.dt, "cfl": 0.5,

@@ -71,7 +71,10 @@ extern "C" {
 
 /* arithmetic of the prediction (the correction is always FP64) */
 #define RIDG_FP64 0
-#define RIDG_FP32_REFINE 1 /* FP32 region solves + FP64-residual iterative refinement (RIDG_SOLVER_REGION) */
+#define RIDG_FP32_REFINE 1 /* REGION: FP32 block solves + FP64-residual iterative refinement (refine_steps
+                              sweeps). PREFACTORED (3D, orders 2-3, n[0] % 16 == 0, n[1] % 4 == 0,
+                              n[2] % 4 == 0): predictions on the matrix cores with FP32 operands and FP32
+                              accumulation (no solve to refine: refine_steps is ignored), FP64 correction */
 
 /* region solver */
 #define RIDG_SOLVER_AUTO 0        /* PREFACTORED for RIDG_FLUX_CONST, REGION otherwise */
@@ -208,6 +211,11 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
                                 state, K_o = sum D_t G_s (the predictions are not stored) */
 #define RIDG_OPT_MFMA 5      /* PREFACTORED: the prediction, correction or composite stencil as stacked-
                                 right-hand-side products on the FP64 matrix cores */
+#define RIDG_OPT_BRICK 6     /* PREFACTORED, 3D, orders 2-3, n[0] % 16 == 0, n[1] % 4 == 0, n[2] % 2 == 0: one
+                                fused kernel per step on 16 x 4 x 2 bricks (state staged in LDS, predictions
+                                of the brick and its upwind halo on the FP64 matrix cores, correction from
+                                LDS). Always used by RIDG_FP32_REFINE PREFACTORED problems (FP32 products,
+                                16 x 4 x 4 bricks) */
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value);
 int ridg_get_option(ridg_t* h, int32_t option, int64_t* value);
 

@@ -44,7 +44,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
 
 struct Layout {
-  size_t q0, q1, w, stage, tens, g, dc, kc, fg, fd, fk, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
+  size_t q0, q1, w, stage, tens, g, dc, kc, fg, fd, fk, fgs, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
       total;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
@@ -104,6 +104,7 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
     L.fg = take(pref ? mfma_fragment_doubles(kMaxBlocks, (int)nt, (int)ns) * 8 : 8);
     L.fd = take(pref ? mfma_fragment_doubles(7, (int)ns, (int)nt) * 8 : 8);
     L.fk = take(pref ? mfma_fragment_doubles(kMaxTapUpdate, (int)ns, (int)ns) * 8 : 8);
+    L.fgs = take(pref ? mfma_fragment_doubles(kMaxBlocks, (int)nt, (int)ns) * 4 : 8);  // G fragments as FP32
   }
   L.taps = take((size_t)kMaxBlocks * 3 * 4);
   int64_t n_dense = 0;
@@ -163,6 +164,10 @@ struct ridg_handle {
   double* Fg = nullptr;  // MFMA fragments of G, Dc and Kc
   double* Fd = nullptr;
   double* Fk = nullptr;
+  float* Fgs = nullptr;  // G fragments in FP32 (reduced-precision brick kernel)
+  BrickTaps brick{};
+  bool brick_ok = false;  // the brick kernel applies to this problem (3D, order 2-3, brick-divisible mesh)
+  int opt_brick = 0;
   int opt_mfma = 0;
   std::vector<int32_t> host_dtaps, host_ktaps;
   int opt_composite = 0;
@@ -271,7 +276,7 @@ std::pair<double, double> flops_model(const ridg_handle* h, double plan_flops) {
 // ---------------------------------------------------------------- autotuner
 namespace {
 std::mutex g_tune_mu;
-std::map<std::string, std::array<int, 5>> g_tune_cache;  // problem key -> {graph, layout, fused, composite, mfma}
+std::map<std::string, std::array<int, 6>> g_tune_cache;  // problem key -> {graph, layout, fused, composite, mfma, brick}
 bool g_tune_file_loaded = false;
 
 std::string tune_key(const ridg_handle* h, int32_t steps) {
@@ -290,21 +295,21 @@ void tune_file_load() {
   FILE* f = std::fopen(path, "r");
   if (!f) return;
   char line[512];
-  while (std::fgets(line, sizeof(line), f)) {  // "<key> graph layout fused composite mfma"
+  while (std::fgets(line, sizeof(line), f)) {  // "<key> graph layout fused composite mfma brick"
     char key[256];
-    int o[5], extra;
-    if (std::sscanf(line, "%255s %d %d %d %d %d %d", key, &o[0], &o[1], &o[2], &o[3], &o[4], &extra) == 6)
-      g_tune_cache[key] = {o[0], o[1], o[2], o[3], o[4]};
+    int o[6], extra;
+    if (std::sscanf(line, "%255s %d %d %d %d %d %d %d", key, &o[0], &o[1], &o[2], &o[3], &o[4], &o[5], &extra) == 7)
+      g_tune_cache[key] = {o[0], o[1], o[2], o[3], o[4], o[5]};
   }
   std::fclose(f);
 }
 
-void tune_file_append(const std::string& key, const std::array<int, 5>& o) {
+void tune_file_append(const std::string& key, const std::array<int, 6>& o) {
   const char* path = std::getenv("RIDG_AUTOTUNE_CACHE");
   if (!path) return;
   FILE* f = std::fopen(path, "a");
   if (!f) return;
-  std::fprintf(f, "%s %d %d %d %d %d\n", key.c_str(), o[0], o[1], o[2], o[3], o[4]);
+  std::fprintf(f, "%s %d %d %d %d %d %d\n", key.c_str(), o[0], o[1], o[2], o[3], o[4], o[5]);
   std::fclose(f);
 }
 }  // namespace
@@ -416,6 +421,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->Fg = (double*)(h->ws + h->L.fg);
   h->Fd = (double*)(h->ws + h->L.fd);
   h->Fk = (double*)(h->ws + h->L.fk);
+  h->Fgs = (float*)(h->ws + h->L.fgs);
+  h->brick_ok = P.solver == RIDG_SOLVER_PREFACTORED && brick_supported(P.d, P.M, P.n, P.precision == RIDG_FP32_REFINE);
   h->taps = (int32_t*)(h->ws + h->L.taps);
   h->plans = (PlanRec*)(h->ws + h->L.plans);
   for (int l = 0; l < kLayouts; ++l) {
@@ -677,12 +684,38 @@ static int ensure_dt_tables(ridg_t* h, double dt) {
   const std::vector<double> fg = mfma_fragments(pf.G.data(), (int)pf.offs.size(), nt, ns);
   const std::vector<double> fd = mfma_fragments(dc.A.data(), (int)dc.offs.size(), ns, nt);
   const std::vector<double> fk = mfma_fragments(kc.A.data(), (int)kc.offs.size(), ns, ns);
+  std::vector<float> fgs(fg.begin(), fg.end());
+  if (h->brick_ok) {  // taps and halos of the brick kernel
+    BrickTaps& b = h->brick;
+    b = BrickTaps{};
+    b.ng = (int)pf.offs.size();
+    b.nd = (int)dc.offs.size();
+    if (b.ng > 8 || b.nd > 4) return fail(RIDG_E_UNSUPPORTED, "brick kernel tap count");
+    for (int i = 0; i < 3; ++i) {
+      int glo = 0, ghi = 0, dlo = 0, dhi = 0;
+      for (int t = 0; t < b.ng; ++t) {
+        b.g[t][i] = (int8_t)pf.offs[t][i];
+        glo = std::min(glo, pf.offs[t][i]);
+        ghi = std::max(ghi, pf.offs[t][i]);
+      }
+      for (int t = 0; t < b.nd; ++t) {
+        b.d[t][i] = (int8_t)dc.offs[t][i];
+        dlo = std::min(dlo, dc.offs[t][i]);
+        dhi = std::max(dhi, dc.offs[t][i]);
+      }
+      b.wlo[i] = (int8_t)dlo;
+      b.whi[i] = (int8_t)dhi;
+      b.qlo[i] = (int8_t)(dlo + glo);
+      b.qhi[i] = (int8_t)(dhi + ghi);
+    }
+  }
   int err = hipMemcpyAsync(h->G, pf.G.data(), pf.G.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Dc, dc.A.data(), dc.A.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Kc, kc.A.data(), kc.A.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Fg, fg.data(), fg.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Fd, fd.data(), fd.size() * 8, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipMemcpyAsync(h->Fk, fk.data(), fk.size() * 8, hipMemcpyHostToDevice, h->stream);
+  if (!err) err = hipMemcpyAsync(h->Fgs, fgs.data(), fgs.size() * 4, hipMemcpyHostToDevice, h->stream);
   if (!err) err = hipStreamSynchronize(h->stream);
   if (err) return hip_fail(err, "upload of the prefactored operators");
   h->g_dt = dt;
@@ -745,6 +778,19 @@ static int direct_step(ridg_t* h, double dt) {
   }
   const int nk = (int)h->host_ktaps.size() / 3, nd = (int)h->host_dtaps.size() / 3;
   const bool mfma = h->opt_mfma != 0;
+  const bool f32 = P.precision == RIDG_FP32_REFINE;
+  if (pref && (h->opt_brick || f32)) {  // fused brick step: matrix-core predictions, FP64 correction
+    int err = launch_brick_step(P.M, f32, h->geom, h->Q[h->cur], h->Q[1 - h->cur],
+                                f32 ? (const void*)h->Fgs : (const void*)h->Fg, h->Dc, h->brick, h->stream);
+    if (err) return hip_fail(err, "brick step launch");
+    if (h->timing) {  // one fused launch: the correction stage is empty
+      err = record_event(h);
+      if (!err) err = record_event(h);
+      if (err) return hip_fail(err, "timing event");
+    }
+    h->cur ^= 1;
+    return RIDG_OK;
+  }
   if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
     int err = mfma ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
                                             h->Q[1 - h->cur], h->Fk, h->host_ktaps.data(), nk, h->stream)
@@ -833,7 +879,8 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
   if (rc) return rc;
   const int warn = stability_warning(h, dt);
   if (warn < 0) return warn;
-  if (h->opt_fused && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && fused_fits(h->P.d, h->P.M, h->P.nel)) {
+  if (h->opt_fused && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && h->P.precision == RIDG_FP64 &&
+      fused_fits(h->P.d, h->P.M, h->P.nel)) {
     int err = launch_fused_prefactored(h->P.d, h->P.M, h->geom, dt, h->Q[h->cur], h->Q[1 - h->cur], h->G,
                                        h->host_taps.data(), h->ntaps, h->dt, n_steps, h->stream);
     if (err) return hip_fail(err, "fused launch");
@@ -867,7 +914,8 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
   for (int i = 0; i < count; ++i) {
     ridg_t* h = handles[i];
     if (!h) return fail(RIDG_E_INVAL, "NULL handle in the batch");
-    if (h->P.solver != RIDG_SOLVER_PREFACTORED) return fail(RIDG_E_UNSUPPORTED, "batched steps need PREFACTORED handles");
+    if (h->P.solver != RIDG_SOLVER_PREFACTORED || h->P.precision != RIDG_FP64)
+      return fail(RIDG_E_UNSUPPORTED, "batched steps need FP64 PREFACTORED handles");
     if (!(dts[i] > 0.0) || !std::isfinite(dts[i])) return fail(RIDG_E_INVAL, "dt must be positive and finite");
     for (int j = 0; j < i; ++j)
       if (handles[j] == h) return fail(RIDG_E_INVAL, "a handle appears twice in the batch");
@@ -997,6 +1045,12 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
         return fail(RIDG_E_UNSUPPORTED, "the MFMA tap kernels need the PREFACTORED solver");
       h->opt_mfma = (int)value;
       break;
+    case RIDG_OPT_BRICK:
+      if (value && !h->brick_ok)
+        return fail(RIDG_E_UNSUPPORTED,
+                    "the brick kernel needs the PREFACTORED solver, 3D, order 2-3 and a brick-divisible mesh");
+      h->opt_brick = (int)value;
+      break;
     default:
       return fail(RIDG_E_INVAL, "unknown option");
   }
@@ -1012,6 +1066,7 @@ int ridg_get_option(ridg_t* h, int32_t option, int64_t* value) {
     case RIDG_OPT_FUSED: *value = h->opt_fused; return RIDG_OK;
     case RIDG_OPT_COMPOSITE: *value = h->opt_composite; return RIDG_OK;
     case RIDG_OPT_MFMA: *value = h->opt_mfma; return RIDG_OK;
+    case RIDG_OPT_BRICK: *value = h->opt_brick; return RIDG_OK;
     default: return fail(RIDG_E_INVAL, "unknown option");
   }
 }
@@ -1033,12 +1088,13 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
       h->opt_fused = it->second[2];
       h->opt_composite = it->second[3];
       h->opt_mfma = it->second[4];
+      h->opt_brick = it->second[5];
       drop_graphs(h);
       if (best_ms_per_step) *best_ms_per_step = -1.0;  // from the cache, not re-measured
       return RIDG_OK;
     }
   }
-  std::vector<std::array<int, 5>> cands;
+  std::vector<std::array<int, 6>> cands;
   const bool region = h->P.solver == RIDG_SOLVER_REGION;
   const bool pref = h->P.solver == RIDG_SOLVER_PREFACTORED;
   const bool fusable = pref && fused_fits(h->P.d, h->P.M, h->P.nel);
@@ -1051,16 +1107,23 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
     layouts = h->P.precision == RIDG_FP64 ? std::vector<int>{0, 1, 2, 3, 4} : std::vector<int>{0, 1};
     if (h->sp_ok) layouts.push_back(kStaticPivotLayout);
   }
-  for (int g = 0; g < 2; ++g)
+  const bool f32_brick = pref && h->P.precision == RIDG_FP32_REFINE;  // the brick kernel is this path
+  for (int g = 0; g < 2; ++g) {
+    if (f32_brick) {
+      cands.push_back({g, 0, 0, 0, 0, 1});
+      continue;
+    }
     for (int l : layouts)
       for (int c = 0; c < (pref ? 2 : 1); ++c)
-        for (int m = 0; m < (pref ? 2 : 1); ++m) cands.push_back({g, l, 0, c, m});
-  if (fusable) cands.push_back({0, 0, 1, 0, 0});
+        for (int m = 0; m < (pref ? 2 : 1); ++m) cands.push_back({g, l, 0, c, m, 0});
+    if (h->brick_ok) cands.push_back({g, 0, 0, 0, 0, 1});
+  }
+  if (fusable && !f32_brick) cands.push_back({0, 0, 1, 0, 0, 0});
   // keep the state: tuning steps run on a copy that is restored afterwards
   const size_t bytes = (size_t)h->P.nel * h->T.ns * 8;
   const int cur0 = h->cur;
   int err = hipMemcpyAsync(h->stage, h->Q[cur0], bytes, hipMemcpyDeviceToDevice, h->stream);
-  std::array<int, 5> pick = {h->opt_graph, h->opt_layout, h->opt_fused, h->opt_composite, h->opt_mfma};
+  std::array<int, 6> pick = {h->opt_graph, h->opt_layout, h->opt_fused, h->opt_composite, h->opt_mfma, h->opt_brick};
   int rc = RIDG_OK;
   // two sweeps over the candidates, each keeping its faster time: the first candidates of a single
   // sweep would run while the clocks still ramp up
@@ -1072,6 +1135,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
     h->opt_fused = cands[c][2];
     h->opt_composite = cands[c][3];
     h->opt_mfma = cands[c][4];
+    h->opt_brick = cands[c][5];
     drop_graphs(h);
     rc = ridg_step(h, 2, dt);  // warm-up (and graph capture)
     if (rc < 0) break;
@@ -1109,6 +1173,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   h->opt_fused = pick[2];
   h->opt_composite = pick[3];
   h->opt_mfma = pick[4];
+  h->opt_brick = pick[5];
   drop_graphs(h);
   if (rc < 0) return rc;
   if (err) return hip_fail(err, "autotune");

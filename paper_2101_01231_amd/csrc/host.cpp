@@ -353,8 +353,10 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     *msg = "RIDG_SOLVER_PREFACTORED needs a constant velocity";
     return RIDG_E_INVAL;
   }
-  if (P.precision == RIDG_FP32_REFINE && solver != RIDG_SOLVER_REGION) {
-    *msg = "RIDG_FP32_REFINE is implemented for RIDG_SOLVER_REGION";
+  if (P.precision == RIDG_FP32_REFINE && solver != RIDG_SOLVER_REGION &&
+      !(solver == RIDG_SOLVER_PREFACTORED && brick_supported(P.d, P.M, P.n, true))) {
+    *msg = "RIDG_FP32_REFINE is implemented for RIDG_SOLVER_REGION, and for RIDG_SOLVER_PREFACTORED in 3D at "
+           "orders 2-3 on meshes with n[0] % 16 == 0, n[1] % 4 == 0, n[2] % 4 == 0";
     return RIDG_E_UNSUPPORTED;
   }
   P.solver = solver;

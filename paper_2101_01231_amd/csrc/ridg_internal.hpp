@@ -297,6 +297,20 @@ int launch_plans_sp(int d, int M, int precision, int refine, const DevGeom& g, d
 // problem's range of V_i0 = v_i(element centre) dt / h_i (inf where a pivot vanishes).
 double static_pivot_growth(const Problem& P, const HostPlanTables& H, int nt, double dt);
 constexpr double kStaticPivotMaxGrowth = 64.0;
+// Fused constant-velocity 3D step on bricks (k_brick.hip): predictions of a brick and its upwind halo
+// on the matrix cores (FP64, or FP32 operands and accumulation when f32), FP64 correction.
+struct BrickTaps {
+  int8_t g[8][3];  // prediction taps (upwind cone)
+  int8_t d[4][3];  // correction taps (own element, inflow faces)
+  int32_t ng, nd;
+  int8_t wlo[3], whi[3];  // prediction region: the brick extended by [wlo, whi] per axis
+  int8_t qlo[3], qhi[3];  // state region: the prediction region extended by the prediction taps
+};
+bool brick_supported(int d, int M, const int n[3], bool f32);
+// frag: mfma_fragments of G (one row tile; doubles, or the same values as floats when f32)
+int launch_brick_step(int M, bool f32, const DevGeom& g, const double* Q, double* Qout, const void* frag,
+                      const double* Dc, const BrickTaps& tp, void* stream);
+
 // Whole run of n_steps on one workgroup (mesh state resident in LDS), constant velocity;
 // returns hipErrorInvalidValue when the mesh does not fit.
 int fused_fits(int d, int M, int64_t nel);

@@ -210,9 +210,11 @@ def rotation_2d(n=512, M=4, seed=2103, cfl=0.5, steps=20):
                     dict(a=a, om=om, cen=cen))
 
 
-def advection_3d(n=128, M=3, seed=2104, cfl=0.5, steps=20):
-    """Workload: 3D advection, v = (1,1,1), sum of 5 periodised Gaussians."""
+def advection_3d(n=128, M=3, seed=2104, cfl=0.5, steps=20, shape=None):
+    """Workload: 3D advection, v = (1,1,1), sum of 5 periodised Gaussians (on an n^3 mesh, or on a
+    mesh of the given shape with the step size of its finest axis)."""
     rng = np.random.default_rng(seed)
+    mesh = tuple(shape) if shape is not None else (n, n, n)
     cen = rng.uniform(0.0, 1.0, (5, 3))
     sig = rng.uniform(0.05, 0.15, 5)
     v = np.array([1.0, 1.0, 1.0])
@@ -222,9 +224,9 @@ def advection_3d(n=128, M=3, seed=2104, cfl=0.5, steps=20):
         for m in range(5):
             s2 = 2 * sig[m] ** 2
             terms.append((1.0, [_periodic_gauss_1d(cen[m, i] + v[i] * t, s2) for i in range(3)]))
-        return project_separable(terms, 3, (n, n, n), M)
-    dt = cfl / n
-    return Workload("3d-advection", 3, (n, n, n), M, ("const", tuple(v)), dt, steps, ex(0.0), ex,
+        return project_separable(terms, 3, mesh, M)
+    dt = cfl / max(mesh)
+    return Workload("3d-advection", 3, mesh, M, ("const", tuple(v)), dt, steps, ex(0.0), ex,
                     dict(cen=cen, sig=sig))
 
 

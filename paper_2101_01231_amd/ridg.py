@@ -30,7 +30,7 @@ ABI_VERSION = 2
 FP64, FP32_REFINE = 0, 1
 SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE = 0, 1, 2, 3
 HOST, DEVICE = 0, 1
-OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE, OPT_MFMA = 1, 2, 3, 4, 5
+OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE, OPT_MFMA, OPT_BRICK = 1, 2, 3, 4, 5, 6
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",

@@ -29,6 +29,8 @@ CASES = {
     "rotation64_m4_20steps": (lambda: I.rotation_2d(n=64, M=4), 20),
     "adv3d12_m3_20steps": (lambda: I.advection_3d(n=12, M=3), 20),
     "adv2d32_m3_100steps": (lambda: I.advection_2d(n=32, M=3), 100),
+    # a mesh the brick kernels tile (16 x 4 x 4 bricks)
+    "adv3d16x8x8_m3_20steps": (lambda: I.advection_3d(M=3, shape=(16, 8, 8)), 20),
 }
 
 

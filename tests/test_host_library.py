@@ -179,3 +179,16 @@ def test_unstable_warning_threshold_follows_von_neumann():
     assert ridg.host_spectral_radius(p1, 1.05 * h, 256) <= 1 + 1e-10
     with pytest.raises(ridg.RidgError):
         ridg.host_spectral_radius(ridg.make_problem(2, (16, 16), 3, flux=ridg.FLUX_ROTATION), 0.01, 16)
+
+
+def test_reduced_precision_constant_velocity_needs_brick_meshes():
+    """RIDG_FP32_REFINE with the prefactored operator is the 3D brick kernel: accepted at orders 2-3 on
+    meshes of 16 x 4 x 4 bricks, refused elsewhere with RIDG_E_UNSUPPORTED."""
+    ok = ridg.make_problem(3, (32, 8, 12), 3, velocity=(1.0, 1.0, 1.0), precision=ridg.FP32_REFINE)
+    assert ridg.workspace_bytes(ok) > 0
+    for bad in (dict(dim=3, n=(24, 8, 8), order=3), dict(dim=3, n=(16, 8, 6), order=3),
+                dict(dim=3, n=(16, 8, 8), order=4), dict(dim=2, n=(32, 32), order=3)):
+        p = ridg.make_problem(**bad, velocity=(1.0, 1.0, 1.0)[:bad["dim"]], precision=ridg.FP32_REFINE)
+        with pytest.raises(ridg.RidgError) as ei:
+            ridg.workspace_bytes(p)
+        assert ei.value.code == ridg.RIDG_E_UNSUPPORTED
