@@ -22,6 +22,8 @@ Paper passages followed (arXiv 2101.01231):
     predicted space-time solution and Rusanov (= upwind for linear
     advection) fluxes.
   * Sec. 4 (terminology): eq. (l2relerror) and eq. (Mratio).
+  * Sec. 3 (Newton on the region system, Jacobian by quadrature, by projection of F'(w) with
+    precomputed triple products, and by perturbation) and eq. (burger2d): ``oracle.burgers``.
 """
 
 from .basis import (  # noqa: F401
