@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define RIDG_ABI_VERSION 2
+#define RIDG_ABI_VERSION 3
 
 /* return codes */
 #define RIDG_OK 0
@@ -58,11 +58,25 @@ extern "C" {
 #define RIDG_W_UNSTABLE 1       /* constant velocity: the step's von Neumann amplification exceeds 1
                                    (ridg_info.spectral_radius > 1 + 1e-10); affine velocity: the CFL
                                    number dt max|v_i|/h_i exceeds 1 */
+#define RIDG_W_NOT_CONVERGED 2  /* RIDG_FLUX_BURGERS (ridg_get_state): the Newton iteration of at least one
+                                   region stopped at newton_max_iter without meeting its tolerance since
+                                   the handle was created or ridg_newton_stats last reset the counters (the
+                                   time step is too large for the local compression of the solution) */
 
 /* velocity field kinds */
 #define RIDG_FLUX_CONST 0    /* v = velocity[0..d-1] */
 #define RIDG_FLUX_ROTATION 1 /* 2D solid-body rotation v = (-(y - c_y), x - c_x), c = rot_center */
 #define RIDG_FLUX_AFFINE 2   /* v_i = velocity[i] + sum_j vel_grad[3 i + j] x_j, vel_grad[3 i + i] = 0 */
+#define RIDG_FLUX_BURGERS 3  /* nonlinear: q_t + sum_i (q^2/2)_{x_i} = 0 (eq. burger2d; the same flux along
+                                every axis). Prediction: Newton iterations on each region system (Sec. 3),
+                                starting from Q^n held constant in time, Jacobian volume term assembled
+                                quasi-quadrature-free (F'(w) projected on the space-time basis, exact
+                                Legendre triple products), face terms by Gauss quadrature; stop when
+                                max|delta| <= 1e-13 max(1, max|W|). Rusanov flux with the wave speed
+                                max(|mean q_a|, |mean q_b|) of the two elements' states at t^n inside the
+                                region and in the correction; own-trace physical flux on the region
+                                boundary. FP64; orders 1-5 in 1D, 1-4 in 2D, 1-2 in 3D; velocity fields
+                                are ignored */
 
 /* basis families (Sec. 2.1) */
 #define RIDG_BASIS_P 0 /* total degree <= order-1 in space and in space-time */
@@ -84,6 +98,9 @@ extern "C" {
                                      a dependency cycle tear one block (multi-right-hand-side elimination plus
                                      one block-sized system), else use the dense path */
 #define RIDG_SOLVER_DENSE 3       /* per element: dense pivoted LU of the whole 3^d theta_T region system */
+#define RIDG_SOLVER_NEWTON 4      /* RIDG_FLUX_BURGERS (its only solver; AUTO selects it): one workgroup per
+                                     region runs the Newton iterations, each a dense pivoted elimination of
+                                     the whole region Jacobian */
 
 /* memory kinds for set/get */
 #define RIDG_HOST 0
@@ -95,7 +112,8 @@ typedef struct ridg_problem {
   int32_t order;        /* M >= 1: basis of total degree M-1; the library implements M <= 5 */
   int32_t basis;        /* RIDG_BASIS_P (RIDG_BASIS_Q gives RIDG_E_UNSUPPORTED) */
   int32_t flux;         /* RIDG_FLUX_* */
-  int32_t reserved0;    /* must be 0 */
+  int32_t newton_max_iter; /* RIDG_FLUX_BURGERS: Newton iterations per region at most (0: 20; <= 100);
+                              must be 0 for the linear fluxes */
   double velocity[3];   /* CONST: v; AFFINE: constant part */
   double rot_center[2]; /* ROTATION: centre; must lie on element boundaries (c_x / h_x, c_y / h_y integers) */
   double vel_grad[9];   /* AFFINE: row-major dv_i/dx_j, diagonal must be 0 */
@@ -121,7 +139,8 @@ typedef struct ridg_info {
    * couplings and an LU-equivalent solve (2/3 theta_T^3 + 2 theta_T^2; the Gauss-Jordan kernels
    * execute about 1.5x the elimination part); DENSE, LU of the whole region. Correction: the volume
    * and face terms of Sec. 2.3 term by term (constant velocity: the precombined tap products). */
-  double flops_predict;     /* per step, prediction */
+  double flops_predict;     /* per step, prediction (RIDG_SOLVER_NEWTON: per Newton iteration of every
+                               region: Jacobian and residual assembly plus the dense elimination) */
   double flops_correct;     /* per step, correction */
   double bytes_predict;     /* per step, prediction: algorithmic HBM bytes (state in, predictions out) */
   double bytes_correct;     /* per step, correction: state in/out, predictions in */
@@ -172,7 +191,8 @@ int ridg_set_state(ridg_t* h, const double* q, size_t count, int32_t where);
  * number dt max|v_i| / h_i exceeds 1. */
 int ridg_step(ridg_t* h, int32_t n_steps, double dt);
 
-/* Copy the state out (layout above); synchronises the stream for RIDG_HOST. */
+/* Copy the state out (layout above); synchronises the stream for RIDG_HOST. RIDG_FLUX_BURGERS: returns
+ * RIDG_W_NOT_CONVERGED (after the copy) when a Newton failure has been counted (RIDG_HOST only). */
 int ridg_get_state(ridg_t* h, double* q, size_t count, int32_t where);
 
 /* The centre predictions W of the current state for step size dt, without the
@@ -251,6 +271,15 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
  * threads or streams) race and must be serialised by the caller. */
 int ridg_advance_static(const ridg_problem* problem, const double* q_in, double* q_out, size_t count,
                         int32_t n_steps, double dt, void* hip_stream);
+
+/* RIDG_FLUX_BURGERS: Newton statistics of the steps (and predictions) queued since the handle was
+ * created or the counters were last reset. Synchronises the stream. max_iters: the most iterations
+ * any region took; total_iters: iterations summed over regions; solves: region solves run; failures:
+ * regions that stopped at newton_max_iter without meeting the tolerance (their last iterate is used).
+ * Any output pointer may be NULL. reset != 0 zeroes the counters after reading them.
+ * RIDG_E_INVAL for the linear fluxes (Sec. 3: Newton's method on the prediction system). */
+int ridg_newton_stats(ridg_t* h, int32_t* max_iters, int64_t* total_iters, int64_t* solves, int64_t* failures,
+                      int32_t reset);
 
 /* Wait for all queued work of the handle. */
 int ridg_synchronize(ridg_t* h);

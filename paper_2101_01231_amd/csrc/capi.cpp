@@ -42,10 +42,12 @@ int hip_fail(int err, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
+constexpr int64_t kNewtonScratchBytes = (int64_t)512 << 20;  // region Jacobians of one Newton launch
 
 struct Layout {
   size_t q0, q1, w, stage, tens, g, dc, kc, fg, fd, fk, fgs, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
-      total;
+      btab, bint, nstats, total;
+  size_t btab_doubles = 0, bint_ints = 0;
   int64_t n_tear = 0;
   size_t ptab_doubles = 0;
   int64_t n_items[kLayouts] = {}, n_dense = 0, scratch_elems = 0;
@@ -125,9 +127,25 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
   L.dense = take(std::max<int64_t>(n_dense, 1) * 4);
   const int64_t N = (int64_t)std::pow(3, P.d) * nt;
   const int64_t per = N * (N + 1) * 8;
-  L.scratch_elems = n_dense > 0 ? std::max<int64_t>(1, std::min<int64_t>(n_dense, kDenseScratchBytes / per)) : 0;
+  const bool newton = P.solver == RIDG_SOLVER_NEWTON;
+  const int64_t n_scr = newton ? P.nel : n_dense;
+  L.scratch_elems =
+      n_scr > 0 ? std::max<int64_t>(1, std::min<int64_t>(n_scr, (newton ? kNewtonScratchBytes : kDenseScratchBytes) / per))
+                : 0;
   L.scratch = take(std::max<int64_t>(L.scratch_elems, 1) * per);
   L.flag = take(256);
+  if (newton) {  // Burgers tables: doubles, then the int32 index tables
+    BurgersHost H;
+    std::string m;
+    if (build_burgers_tables(P, make_basis(P.d, P.M), &H, &m) == RIDG_OK) {
+      L.btab_doubles = H.psiv.size() + H.dpsivw.size() + H.projw.size() + H.dphivw.size() + H.psif.size() +
+                       H.psifw.size() + H.phifw.size() + H.bval.size();
+      L.bint_ints = H.bptr.size() + H.bp.size() + H.lift.size();
+    }
+  }
+  L.btab = take(std::max<size_t>(L.btab_doubles, 1) * 8);
+  L.bint = take(std::max<size_t>(L.bint_ints, 1) * 4);
+  L.nstats = take(64);
   if (P.solver == RIDG_SOLVER_REGION) {
     const size_t nn = nt * nt;
     L.ptab_doubles = ((size_t)1 << (2 * P.d)) * nn + (size_t)P.d * 4 * nn + 2 * (size_t)P.d * 2 * nn + 2 * nt;
@@ -185,6 +203,8 @@ struct ridg_handle {
   int32_t* telems = nullptr;
   double* scratch = nullptr;
   int32_t* flag = nullptr;
+  BurgersDev bd{};            // RIDG_SOLVER_NEWTON: device view of the Burgers tables
+  int32_t* nstats = nullptr;  // Newton counters: max iterations, failures, total iterations, solves
   DevGeom geom{};
   ridg_info info{};
   PlanTables pt{};
@@ -434,6 +454,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->telems = (int32_t*)(h->ws + h->L.telems);
   h->scratch = (double*)(h->ws + h->L.scratch);
   h->flag = (int32_t*)(h->ws + h->L.flag);
+  h->nstats = (int32_t*)(h->ws + h->L.nstats);
   // upload tensors
   const RefTensors& T = h->T;
   std::vector<double> tens;
@@ -478,6 +499,53 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
     err = hipMemcpyAsync(h->dense, all.data(), all.size() * 4, hipMemcpyHostToDevice, h->stream);
     if (!err) err = hipStreamSynchronize(h->stream);
   }
+  BurgersHost BH;  // kept alive until the uploads below have completed
+  if (!err && P.solver == RIDG_SOLVER_NEWTON) {
+    std::string m;
+    int brc = build_burgers_tables(P, h->B, &BH, &m);
+    if (brc) {
+      delete h;
+      return fail(brc, m);
+    }
+    std::vector<double> bt;
+    bt.reserve(h->L.btab_doubles);
+    double* bbase = (double*)(h->ws + h->L.btab);
+    auto pushd = [&](const std::vector<double>& v) {
+      const double* at = bbase + bt.size();
+      bt.insert(bt.end(), v.begin(), v.end());
+      return at;
+    };
+    std::vector<int32_t> bi;
+    bi.reserve(h->L.bint_ints);
+    int32_t* ibase = (int32_t*)(h->ws + h->L.bint);
+    auto pushi = [&](const std::vector<int32_t>& v) {
+      const int32_t* at = ibase + bi.size();
+      bi.insert(bi.end(), v.begin(), v.end());
+      return at;
+    };
+    BurgersDev& bd = h->bd;
+    bd.Tt = h->dt.Tt;
+    bd.Cc = h->dt.Cc;
+    bd.psiv = pushd(BH.psiv);
+    bd.dpsivw = pushd(BH.dpsivw);
+    bd.projw = pushd(BH.projw);
+    bd.dphivw = pushd(BH.dphivw);
+    bd.psif = pushd(BH.psif);
+    bd.psifw = pushd(BH.psifw);
+    bd.phifw = pushd(BH.phifw);
+    bd.bval = pushd(BH.bval);
+    bd.bptr = pushi(BH.bptr);
+    bd.bp = pushi(BH.bp);
+    bd.lift = pushi(BH.lift);
+    if (bt.size() != h->L.btab_doubles || bi.size() != h->L.bint_ints) {
+      delete h;
+      return fail(RIDG_E_NOMEM, "Burgers table layout");
+    }
+    err = hipMemcpyAsync(bbase, bt.data(), bt.size() * 8, hipMemcpyHostToDevice, h->stream);
+    if (!err) err = hipMemcpyAsync(ibase, bi.data(), bi.size() * 4, hipMemcpyHostToDevice, h->stream);
+    if (!err) err = hipStreamSynchronize(h->stream);
+  }
+  if (!err) err = hipMemsetAsync(h->nstats, 0, 64, h->stream);
   if (!err && P.solver == RIDG_SOLVER_REGION && (h->L.n_dense || h->L.n_tear) && h->L.n_items[0]) {
     err = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
     if (!err) err = hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming);
@@ -520,6 +588,21 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   auto fl = flops_model(h, plan_flops);
   I.flops_predict = fl.first;
   I.flops_correct = fl.second;
+  if (P.solver == RIDG_SOLVER_NEWTON) {  // per Newton iteration of every region, and per correction
+    const double nt = T.nt, ns = T.ns, nb = std::pow(3.0, P.d), N = nb * nt, nf = 2.0 * P.d;
+    const double q = burgers_q(P.M), nq = std::pow(q, P.d + 1), nqf = std::pow(q, P.d);
+    double nnz = 0.0;
+    {
+      BurgersHost H2;
+      std::string m2;
+      if (build_burgers_tables(P, h->B, &H2, &m2) == RIDG_OK) nnz = (double)H2.bp.size();
+    }
+    const double fma_points = nb * nt * (nq + nf * nqf) + nb * nt * nq;              // point values, projection
+    const double fma_rows = N * (nt + ns + P.d * nq + nf * nqf * (2.0 * nt + 1.0)) + nb * nnz;  // assembly
+    const double fma_solve = N * N * N / 3.0 + N * N;                                      // elimination, back-solve
+    I.flops_predict = (double)P.nel * 2.0 * (fma_points + fma_rows + fma_solve);
+    I.flops_correct = (double)P.nel * 2.0 * (nq * (nt + P.d * ns) + nf * nqf * (2.0 * nt + ns));
+  }
   I.bytes_predict = (double)P.nel * 8.0 * (T.ns + T.nt);
   I.bytes_correct = (double)P.nel * 8.0 * (2.0 * T.ns + T.nt);
   I.bytes_composite = (double)P.nel * 8.0 * 2.0 * T.ns;
@@ -567,6 +650,25 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out) {
   return RIDG_OK;
 }
 
+int ridg_newton_stats(ridg_t* h, int32_t* max_iters, int64_t* total_iters, int64_t* solves, int64_t* failures,
+                      int32_t reset) {
+  if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
+  if (h->P.solver != RIDG_SOLVER_NEWTON) return fail(RIDG_E_INVAL, "Newton statistics need RIDG_FLUX_BURGERS");
+  int32_t buf[6] = {0, 0, 0, 0, 0, 0};
+  int err = hipMemcpyAsync(buf, h->nstats, sizeof(buf), hipMemcpyDeviceToHost, h->stream);
+  if (!err) err = hipStreamSynchronize(h->stream);
+  if (!err && reset) err = hipMemsetAsync(h->nstats, 0, 64, h->stream);
+  if (err) return hip_fail(err, "ridg_newton_stats");
+  int64_t tot, nsol;
+  std::memcpy(&tot, buf + 2, 8);
+  std::memcpy(&nsol, buf + 4, 8);
+  if (max_iters) *max_iters = buf[0];
+  if (failures) *failures = buf[1];
+  if (total_iters) *total_iters = tot;
+  if (solves) *solves = nsol;
+  return RIDG_OK;
+}
+
 int ridg_synchronize(ridg_t* h) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
   return check_hip(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
@@ -604,8 +706,12 @@ int ridg_get_state(ridg_t* h, double* q, size_t count, int32_t where) {
   if (where == RIDG_HOST) {
     int err = launch_soa_to_aos(h->Q[h->cur], h->stage, h->P.nel, h->T.ns, h->stream);
     if (!err) err = hipMemcpyAsync(q, h->stage, count * 8, hipMemcpyDeviceToHost, h->stream);
+    int32_t nfail = 0;
+    if (!err && h->P.solver == RIDG_SOLVER_NEWTON)
+      err = hipMemcpyAsync(&nfail, h->nstats + 1, 4, hipMemcpyDeviceToHost, h->stream);
     if (!err) err = hipStreamSynchronize(h->stream);
-    return check_hip(err, "ridg_get_state");
+    if (err) return check_hip(err, "ridg_get_state");
+    return nfail ? RIDG_W_NOT_CONVERGED : RIDG_OK;
   }
   if (where == RIDG_DEVICE)
     return check_hip(launch_soa_to_aos(h->Q[h->cur], q, h->P.nel, h->T.ns, h->stream), "ridg_get_state");
@@ -645,6 +751,7 @@ static int ensure_plan_tables(ridg_t* h, double dt) {
 // Warning state of a step of size dt: the von Neumann amplification of the composed step
 // (constant velocity, any solver; analysed once per dt), else the CFL number.
 static int stability_warning(ridg_t* h, double dt) {
+  if (h->P.flux == RIDG_FLUX_BURGERS) return RIDG_OK;  // reported through the Newton counters
   if (h->P.flux != RIDG_FLUX_CONST) return cfl_number(h->P, dt) > 1.0 ? RIDG_W_UNSTABLE : RIDG_OK;
   if (dt != h->vn_dt) {
     std::string msg;
@@ -735,7 +842,10 @@ static int record_event(ridg_t* h) {
 static int run_predict(ridg_t* h, const double* Q, double dt) {
   const Problem& P = h->P;
   int err = 0;
-  if (P.solver == RIDG_SOLVER_PREFACTORED) {
+  if (P.solver == RIDG_SOLVER_NEWTON) {
+    err = launch_burgers_predict(P.d, P.M, h->geom, dt, Q, h->W, h->bd, P.nel, h->scratch, h->L.scratch_elems,
+                                 P.newton_max, h->nstats, h->stream);
+  } else if (P.solver == RIDG_SOLVER_PREFACTORED) {
     err = launch_predict_prefactored(P.d, P.M, h->geom, Q, h->W, h->G, h->host_taps.data(), h->ntaps, h->stream);
   } else if (P.solver == RIDG_SOLVER_REGION) {
     // cyclic regions (tear and dense kernels) run beside the plan kernel on a forked stream
@@ -816,6 +926,8 @@ static int direct_step(ridg_t* h, double dt) {
   else if (pref && !h->opt_composite)
     err = launch_tap_update(P.d, P.M, 0, h->geom, h->W, h->Q[h->cur], h->Q[1 - h->cur], h->Dc, h->host_dtaps.data(),
                             nd, h->stream);
+  else if (P.solver == RIDG_SOLVER_NEWTON)
+    err = launch_burgers_correct(P.d, P.M, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->bd, h->stream);
   else if (!pref)
     err = launch_correct(P.d, P.M, P.flux, h->geom, dt, h->Q[h->cur], h->W, h->Q[1 - h->cur], h->dt, h->stream);
   if (err) return hip_fail(err, "correction launch");
@@ -1018,6 +1130,8 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
   const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : 1;
   if (value < 0 || value > vmax) return fail(RIDG_E_INVAL, "option value out of range");
+  if (h->P.solver == RIDG_SOLVER_NEWTON && value)
+    return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no execution options");
   int err = hipStreamSynchronize(h->stream);
   if (err) return hip_fail(err, "hipStreamSynchronize");
   switch (option) {
@@ -1077,6 +1191,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   if (steps < 2 || steps > 100000) return fail(RIDG_E_INVAL, "steps must be in 2..100000");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be positive and finite");
   if (h->timing) return fail(RIDG_E_INVAL, "switch stage timing off before autotuning");
+  if (h->P.solver == RIDG_SOLVER_NEWTON) return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no options to tune");
   const std::string key = tune_key(h, steps);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1213,6 +1328,7 @@ int ridg_host_region_matrix(const ridg_problem* problem, int64_t element, double
   std::string msg;
   int rc = resolve_problem(problem, &P, &msg);
   if (rc) return fail(rc, msg);
+  if (P.flux == RIDG_FLUX_BURGERS) return fail(RIDG_E_INVAL, "the Burgers region system depends on the state");
   if (!a) return fail(RIDG_E_INVAL, "a is NULL");
   if (element < 0 || element >= P.nel) return fail(RIDG_E_INVAL, "element out of range");
   if (!std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt not finite");

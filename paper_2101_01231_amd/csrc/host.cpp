@@ -242,10 +242,6 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     *msg = "unknown basis";
     return RIDG_E_INVAL;
   }
-  if (p->reserved0 != 0) {
-    *msg = "reserved0 must be 0";
-    return RIDG_E_INVAL;
-  }
   P.nel = 1;
   for (int i = 0; i < 3; ++i) {
     if (i < P.d) {
@@ -313,6 +309,8 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     v.a[1] = -cx;
     v.g[0][1] = -1.0;
     v.g[1][0] = 1.0;
+  } else if (P.flux == RIDG_FLUX_BURGERS) {
+    // nonlinear flux q^2 / 2 along every axis: the velocity fields are not used
   } else if (P.flux == RIDG_FLUX_AFFINE) {
     for (int i = 0; i < P.d; ++i) {
       v.a[i] = p->velocity[i];
@@ -344,9 +342,33 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     return RIDG_E_INVAL;
   }
   int solver = p->solver;
-  if (solver == RIDG_SOLVER_AUTO) solver = (P.flux == RIDG_FLUX_CONST) ? RIDG_SOLVER_PREFACTORED : RIDG_SOLVER_REGION;
-  if (solver < RIDG_SOLVER_PREFACTORED || solver > RIDG_SOLVER_DENSE) {
+  if (solver == RIDG_SOLVER_AUTO)
+    solver = (P.flux == RIDG_FLUX_CONST) ? RIDG_SOLVER_PREFACTORED
+                                         : (P.flux == RIDG_FLUX_BURGERS ? RIDG_SOLVER_NEWTON : RIDG_SOLVER_REGION);
+  if (solver < RIDG_SOLVER_PREFACTORED || solver > RIDG_SOLVER_NEWTON) {
     *msg = "unknown solver";
+    return RIDG_E_INVAL;
+  }
+  if ((solver == RIDG_SOLVER_NEWTON) != (P.flux == RIDG_FLUX_BURGERS)) {
+    *msg = "RIDG_FLUX_BURGERS is solved by (and only by) RIDG_SOLVER_NEWTON";
+    return RIDG_E_INVAL;
+  }
+  if (P.flux == RIDG_FLUX_BURGERS) {
+    if (p->newton_max_iter < 0 || p->newton_max_iter > 100) {
+      *msg = "newton_max_iter must be in 0..100";
+      return RIDG_E_INVAL;
+    }
+    P.newton_max = p->newton_max_iter ? p->newton_max_iter : 20;
+    if (P.precision != RIDG_FP64) {
+      *msg = "RIDG_FLUX_BURGERS runs in FP64";
+      return RIDG_E_UNSUPPORTED;
+    }
+    if (!burgers_supported(P.d, P.M)) {
+      *msg = "RIDG_FLUX_BURGERS is implemented for orders 1-5 in 1D, 1-4 in 2D and 1-2 in 3D";
+      return RIDG_E_UNSUPPORTED;
+    }
+  } else if (p->newton_max_iter != 0) {
+    *msg = "newton_max_iter must be 0 for the linear fluxes";
     return RIDG_E_INVAL;
   }
   if (solver == RIDG_SOLVER_PREFACTORED && P.flux != RIDG_FLUX_CONST) {
@@ -362,7 +384,7 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
   P.solver = solver;
   // every face must have one upwind side
   int idx[3] = {0, 0, 0};
-  if (P.flux != RIDG_FLUX_CONST) {
+  if (P.flux != RIDG_FLUX_CONST && P.flux != RIDG_FLUX_BURGERS) {
     // v_i depends on x_j (j != i) only through element rows: scan each axis line once
     for (int i = 0; i < P.d; ++i) {
       int64_t lines = P.nel / P.n[i];

@@ -1,0 +1,415 @@
+// Burgers equation q_t + sum_i (q^2/2)_{x_i} = 0 (eq. burger2d): Newton prediction on each region
+// (Sec. 3) and the nonlinear flux-form correction (Sec. 2.3).
+//
+// Prediction: one workgroup per region of 3^d elements keeps the iterate W (3^d theta_T unknowns) in
+// LDS. Each Newton iteration
+//   1. evaluates w = Psi^T W_r at the volume and face Gauss points of every region element,
+//   2. projects F'(w) = w on the space-time basis (eq. Jacproj; quadrature once per mode),
+//   3. assembles one row of [J | R] per thread in a per-workgroup scratch matrix: time term and
+//      causal source from the exact tensors, volume flux residual by quadrature, volume Jacobian
+//      quasi-quadrature-free (sum_p beta^i_{k l p} F'_p with the exact triple products, eq.
+//      Jacobian2), face terms (Rusanov inside the region, own-trace physical flux on its boundary)
+//      and their Jacobian blocks by face quadrature,
+//   4. solves J delta = R by Gaussian elimination with partial pivoting and updates W <- W - delta,
+//      until max|delta| <= 1e-13 max(1, max|W|) or the iteration limit.
+// Only the centre's W is written. The Rusanov wave speed of a face is max(|mean q_a|, |mean q_b|)
+// from the two elements' states at t^n (fixed during the iteration).
+//
+// Correction: one thread per element, volume term and face fluxes by quadrature from the element's
+// own prediction and its face neighbours' predictions.
+#include "kernels_common.hpp"
+
+namespace ridg {
+
+namespace {
+
+constexpr double kNewtonTol = 1e-13;
+constexpr int kBurgersThreads = 256;
+
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+template <int D, int M>
+struct BCfg {
+  static constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NB = pow3(D), N = NB * NT, LD = N + 1;
+  static constexpr int Q = burgers_q(M), NQ = ipow(Q, D + 1), NQF = ipow(Q, D), NF = 2 * D;
+};
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+}  // namespace
+
+// Point values of every region element's iterate at the volume and face points, then the projection
+// of F'(w) = w on Psi (eq. Jacproj).
+template <int D, int M>
+__device__ __noinline__ void newton_points(const BurgersDev& t, const double* s_W, double* s_wv, double* s_wf,
+                                           double* s_fp) {
+  using C = BCfg<D, M>;
+  constexpr int NT = C::NT, NB = C::NB, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  const int tid = threadIdx.x;
+  for (int x = tid; x < NB * NQ; x += kBurgersThreads) {
+    const int r = x / NQ, pt = x % NQ;
+    double v = 0.0;
+    for (int l = 0; l < NT; ++l) v = fma(t.psiv[l * NQ + pt], s_W[r * NT + l], v);
+    s_wv[x] = v;
+  }
+  for (int x = tid; x < NB * NF * NQF; x += kBurgersThreads) {
+    const int r = x / (NF * NQF), f = (x / NQF) % NF, pf = x % NQF;
+    double v = 0.0;
+    for (int l = 0; l < NT; ++l) v = fma(t.psif[(f * NT + l) * NQF + pf], s_W[r * NT + l], v);
+    s_wf[x] = v;
+  }
+  __syncthreads();
+  for (int x = tid; x < NB * NT; x += kBurgersThreads) {
+    const int r = x / NT, p = x % NT;
+    double v = 0.0;
+    for (int pt = 0; pt < NQ; ++pt) v = fma(t.projw[p * NQ + pt], s_wv[r * NQ + pt], v);
+    s_fp[x] = v;
+  }
+  __syncthreads();
+}
+
+// Row R = (r, k) of [J | R] (one thread): time term and causal source, volume flux residual by
+// quadrature, volume Jacobian from the triple products (eq. Jacobian2), face terms and their Jacobian
+// blocks by face quadrature.
+template <int D, int M>
+__device__ __noinline__ void newton_row(const BurgersDev& t, double c0, double c1, double c2, int R,
+                                        const double* s_W, const double* s_q, const double* s_wv,
+                                        const double* s_wf, const double* s_fp, double* __restrict__ row) {
+  using C = BCfg<D, M>;
+  constexpr int NS = C::NS, NT = C::NT, N = C::N, LD = C::LD, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  const int r = R / NT, k = R % NT;
+  for (int j = 0; j < LD; ++j) row[j] = 0.0;
+  double dg[NT];
+  double res = 0.0;
+#pragma unroll
+  for (int l = 0; l < NT; ++l) {
+    dg[l] = t.Tt[k * NT + l];
+    res = fma(dg[l], s_W[r * NT + l], res);
+  }
+  for (int j = 0; j < NS; ++j) res = fma(-t.Cc[k * NS + j], s_q[r * NS + j], res);
+#pragma unroll 1
+  for (int i = 0; i < D; ++i) {
+    const double cc = i == 0 ? c0 : (i == 1 ? c1 : c2);
+    double v = 0.0;  // int int d_xi_i Psi_k F(w)
+    const double* dw = t.dpsivw + ((size_t)i * NT + k) * NQ;
+#pragma unroll 4
+    for (int pt = 0; pt < NQ; ++pt) {
+      const double w = s_wv[r * NQ + pt];
+      v = fma(dw[pt], 0.5 * w * w, v);
+    }
+    res = fma(-cc, v, res);
+    const int32_t* bptr = t.bptr + ((size_t)i * NT + k) * NT;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) {
+      double sm = 0.0;
+      for (int q = bptr[l]; q < bptr[l + 1]; ++q) sm = fma(t.bval[q], s_fp[r * NT + t.bp[q]], sm);
+      dg[l] = fma(-cc, sm, dg[l]);
+    }
+  }
+  // region offset digits of r (o_0 slowest)
+  const int d0 = (D == 1) ? r : (D == 2 ? r / 3 : r / 9);
+  const int d1 = (D == 2) ? r % 3 : (r / 3) % 3;
+  const int d2 = r % 3;
+#pragma unroll 1
+  for (int f = 0; f < NF; ++f) {
+    const int i = f >> 1, fo = f ^ 1;
+    const double cc = i == 0 ? c0 : (i == 1 ? c1 : c2);
+    const double s = (f & 1) ? 1.0 : -1.0;
+    const int oi = (i == 0 ? d0 : (i == 1 ? d1 : d2)) + ((f & 1) ? 1 : -1);
+    const bool inside = oi >= 0 && oi <= 2;
+    const int stride = (i == D - 1) ? 1 : (i == D - 2 ? 3 : 9);
+    const int r2 = inside ? r + ((f & 1) ? stride : -stride) : r;
+    const double al = inside ? fmax(fabs(s_q[r * NS]), fabs(s_q[r2 * NS])) : 0.0;
+    double nb[NT];
+#pragma unroll
+    for (int l = 0; l < NT; ++l) nb[l] = 0.0;
+    const double* wk = t.psifw + ((size_t)f * NT + k) * NQF;
+#pragma unroll 1
+    for (int pf = 0; pf < NQF; ++pf) {
+      const double a = s_wf[(r * NF + f) * NQF + pf];
+      double H, da, db = 0.0;
+      if (inside) {
+        const double b = s_wf[(r2 * NF + fo) * NQF + pf];
+        H = 0.5 * s * (0.5 * a * a + 0.5 * b * b) - 0.5 * al * (b - a);
+        da = 0.5 * s * a + 0.5 * al;
+        db = 0.5 * s * b - 0.5 * al;
+      } else {
+        H = 0.5 * s * a * a;
+        da = s * a;
+      }
+      const double cw = cc * wk[pf];
+      res = fma(cw, H, res);
+      const double* pown = t.psif + (size_t)f * NT * NQF + pf;
+      const double* pnbr = t.psif + (size_t)fo * NT * NQF + pf;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        dg[l] = fma(cw * da, pown[l * NQF], dg[l]);
+        nb[l] = fma(cw * db, pnbr[l * NQF], nb[l]);
+      }
+    }
+    if (inside) {
+#pragma unroll
+      for (int l = 0; l < NT; ++l) row[r2 * NT + l] = nb[l];
+    }
+  }
+#pragma unroll
+  for (int l = 0; l < NT; ++l) row[r * NT + l] = dg[l];
+  row[N] = res;
+}
+
+// Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A, then back
+// substitution into s_x. Pivot: the row of largest |A[r][c]|, compared on a 32-bit key (FP32 image of
+// |A[r][c]| with the low bits replaced by the row, ties to the lowest row), reduced within each
+// wavefront and then across wavefronts in LDS.
+template <int N>
+__device__ __noinline__ void newton_solve(double* __restrict__ A, double* s_x, double* s_l, double* s_piv,
+                                          int* s_key) {
+  constexpr int LD = N + 1, NW = kBurgersThreads / 64;
+  constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : 10);
+  constexpr unsigned RMASK = (1u << RB) - 1u;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int c = 0; c < N; ++c) {
+    unsigned key = 0u;
+    for (int Rr = c + tid; Rr < N; Rr += kBurgersThreads) {
+      const unsigned kk = (__float_as_uint((float)fabs(A[(size_t)Rr * LD + c])) & ~RMASK) | (RMASK - (unsigned)Rr);
+      key = max(key, kk);
+    }
+    key = seg_max_pow2<64>(key);
+    if (lane == 0) s_key[wid] = (int)key;
+    __syncthreads();
+    unsigned best = 0u;
+    for (int w = 0; w < NW; ++w) best = max(best, (unsigned)s_key[w]);
+    const int p = (int)(RMASK - (best & RMASK));
+    for (int j = c + tid; j < LD; j += kBurgersThreads) {
+      const double vc = A[(size_t)c * LD + j], vp = A[(size_t)p * LD + j];
+      if (p != c) {
+        A[(size_t)c * LD + j] = vp;
+        A[(size_t)p * LD + j] = vc;
+      }
+      s_piv[j] = vp;
+    }
+    __syncthreads();
+    const double inv = 1.0 / s_piv[c];
+    for (int Rr = c + 1 + tid; Rr < N; Rr += kBurgersThreads) s_l[Rr] = A[(size_t)Rr * LD + c] * inv;
+    __syncthreads();
+    const int rows = N - c - 1, cols = LD - c - 1;
+    for (int q = tid; q < rows * cols; q += kBurgersThreads) {
+      const int Rr = c + 1 + q / cols, j = c + 1 + q % cols;
+      A[(size_t)Rr * LD + j] = fma(-s_l[Rr], s_piv[j], A[(size_t)Rr * LD + j]);
+    }
+    __syncthreads();
+  }
+  for (int c = N - 1; c >= 0; --c) {
+    if (tid == 0) s_x[c] = A[(size_t)c * LD + N] / A[(size_t)c * LD + c];
+    __syncthreads();
+    const double xc = s_x[c];
+    for (int Rr = tid; Rr < c; Rr += kBurgersThreads)
+      A[(size_t)Rr * LD + N] = fma(-A[(size_t)Rr * LD + c], xc, A[(size_t)Rr * LD + N]);
+    __syncthreads();
+  }
+}
+
+template <int D, int M>
+__global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeom g, double dt,
+                                                                          const double* __restrict__ Qs,
+                                                                          double* __restrict__ W, BurgersDev t,
+                                                                          int64_t first, int64_t nel,
+                                                                          double* __restrict__ scratch, int max_iter,
+                                                                          int32_t* __restrict__ stats) {
+  using C = BCfg<D, M>;
+  constexpr int NS = C::NS, NT = C::NT, NB = C::NB, N = C::N, LD = C::LD, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  const int64_t e = first + blockIdx.x;
+  if (e >= nel) return;
+  double* A = scratch + (size_t)blockIdx.x * N * LD;  // [N][N + 1]: Jacobian | residual
+  __shared__ double s_W[N];
+  __shared__ double s_q[NB * NS];
+  __shared__ double s_wv[NB * NQ];
+  __shared__ double s_wf[NB * NF * NQF];
+  __shared__ double s_fp[NB * NT];
+  __shared__ double s_x[N];
+  __shared__ double s_l[N];
+  __shared__ double s_piv[LD];
+  __shared__ int s_key[kBurgersThreads / 64];
+  __shared__ double s_red[2][kBurgersThreads / 64];
+  __shared__ int64_t s_ge[NB];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  constexpr int NW = kBurgersThreads / 64;
+  if (tid < NB) {
+    int base[3];
+    elem_idx(g, e, base);
+    int o[3] = {0, 0, 0}, c = tid;
+    for (int i = D - 1; i >= 0; --i) {
+      o[i] = c % 3 - 1;
+      c /= 3;
+    }
+    s_ge[tid] = elem_lin(g, base[0] + o[0], base[1] + o[1], base[2] + o[2]);
+  }
+  __syncthreads();
+  for (int x = tid; x < NB * NS; x += kBurgersThreads) {
+    const int r = x / NS, j = x % NS;
+    s_q[x] = Qs[(int64_t)j * nel + s_ge[r]];
+  }
+  for (int x = tid; x < N; x += kBurgersThreads) s_W[x] = 0.0;
+  __syncthreads();
+  for (int x = tid; x < NB * NS; x += kBurgersThreads) {  // W^(0): the state held constant in time
+    const int r = x / NS, j = x % NS;
+    s_W[r * NT + t.lift[j]] = s_q[x];
+  }
+  __syncthreads();
+  const double c0 = dt / g.h0, c1 = dt / g.h1, c2 = dt / g.h2;
+  int it = 0;
+  bool converged = false;
+  while (it < max_iter && !converged) {
+    ++it;
+    newton_points<D, M>(t, s_W, s_wv, s_wf, s_fp);
+    for (int R = tid; R < N; R += kBurgersThreads)
+      newton_row<D, M>(t, c0, c1, c2, R, s_W, s_q, s_wv, s_wf, s_fp, A + (size_t)R * LD);
+    __syncthreads();
+    newton_solve<N>(A, s_x, s_l, s_piv, s_key);
+    // update and convergence test (uniform across the workgroup)
+    double md = 0.0, mw = 0.0;
+    for (int x = tid; x < N; x += kBurgersThreads) {
+      const double w = s_W[x] - s_x[x];
+      s_W[x] = w;
+      md = fmax(md, fabs(s_x[x]));
+      mw = fmax(mw, fabs(w));
+    }
+    md = wave_max(md);
+    mw = wave_max(mw);
+    if (lane == 0) {
+      s_red[0][wid] = md;
+      s_red[1][wid] = mw;
+    }
+    __syncthreads();
+    md = 0.0;
+    mw = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      md = fmax(md, s_red[0][w]);
+      mw = fmax(mw, s_red[1][w]);
+    }
+    converged = md <= kNewtonTol * fmax(1.0, mw);
+    __syncthreads();
+  }
+  const int centre = (NB - 1) / 2;
+  for (int k = tid; k < NT; k += kBurgersThreads) W[(int64_t)k * nel + e] = s_W[centre * NT + k];
+  if (tid == 0) {
+    atomicMax(stats, it);
+    if (!converged) atomicAdd(stats + 1, 1);
+    atomicAdd((unsigned long long*)(stats + 2), (unsigned long long)it);
+    atomicAdd((unsigned long long*)(stats + 4), 1ull);
+  }
+}
+
+template <int D, int M>
+__global__ __launch_bounds__(256) void burgers_correct_kernel(DevGeom g, double dt, const double* __restrict__ Qs,
+                                                              const double* __restrict__ W, double* __restrict__ Qout,
+                                                              BurgersDev t) {
+  using C = BCfg<D, M>;
+  constexpr int NS = C::NS, NT = C::NT, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nel) return;
+  const double ci[3] = {dt / g.h0, dt / g.h1, dt / g.h2};
+  double we[NT], acc[NS];
+#pragma unroll
+  for (int l = 0; l < NT; ++l) we[l] = W[(int64_t)l * nel + e];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc[k] = 0.0;
+  // volume: sum_i c_i int int d_xi_i Phi_k F(w_e)
+  for (int pt = 0; pt < NQ; ++pt) {
+    double w = 0.0;
+#pragma unroll
+    for (int l = 0; l < NT; ++l) w = fma(t.psiv[l * NQ + pt], we[l], w);
+    const double F = 0.5 * w * w;
+    for (int i = 0; i < D; ++i) {
+      const double cf = ci[i] * F;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) acc[k] = fma(cf, t.dphivw[((size_t)i * NS + k) * NQ + pt], acc[k]);
+    }
+  }
+  // faces: - sum_f c_i int int Phi_k|_f H(w_e, w_nbr)
+  int idx[3];
+  elem_idx(g, e, idx);
+  const double qe0 = Qs[e];
+  for (int f = 0; f < NF; ++f) {
+    const int i = f >> 1, fo = f ^ 1;
+    const double s = (f & 1) ? 1.0 : -1.0;
+    int j[3] = {idx[0], idx[1], idx[2]};
+    j[i] += (f & 1) ? 1 : -1;
+    const int64_t en = elem_lin(g, j[0], j[1], j[2]);
+    double wn[NT];
+#pragma unroll
+    for (int l = 0; l < NT; ++l) wn[l] = W[(int64_t)l * nel + en];
+    const double al = fmax(fabs(qe0), fabs(Qs[en]));
+    for (int pf = 0; pf < NQF; ++pf) {
+      double a = 0.0, b = 0.0;
+#pragma unroll
+      for (int l = 0; l < NT; ++l) {
+        a = fma(t.psif[((size_t)f * NT + l) * NQF + pf], we[l], a);
+        b = fma(t.psif[((size_t)fo * NT + l) * NQF + pf], wn[l], b);
+      }
+      const double H = 0.5 * s * (0.5 * a * a + 0.5 * b * b) - 0.5 * al * (b - a);
+      const double ch = -ci[i] * H;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) acc[k] = fma(ch, t.phifw[((size_t)f * NS + k) * NQF + pf], acc[k]);
+    }
+  }
+  const double sc = 1.0 / (double)(1 << D);
+#pragma unroll
+  for (int k = 0; k < NS; ++k) Qout[(int64_t)k * nel + e] = fma(acc[k], sc, Qs[(int64_t)k * nel + e]);
+}
+
+namespace {
+
+template <int D, int M>
+int burgers_predict_dm(const DevGeom& g, double dt, const double* Q, double* W, const BurgersDev& t, int64_t nel,
+                       double* scratch, int64_t scratch_elems, int max_iter, int32_t* stats, void* stream) {
+  for (int64_t first = 0; first < nel; first += scratch_elems) {
+    const int64_t chunk = (nel - first < scratch_elems) ? nel - first : scratch_elems;
+    hipLaunchKernelGGL((burgers_predict_kernel<D, M>), dim3((unsigned)chunk), dim3(kBurgersThreads), 0,
+                       (hipStream_t)stream, g, dt, Q, W, t, first, nel, scratch, max_iter, stats);
+    const int err = (int)hipGetLastError();
+    if (err) return err;
+  }
+  return 0;
+}
+
+template <int D, int M>
+int burgers_correct_dm(const DevGeom& g, double dt, const double* Q, const double* W, double* Qout,
+                       const BurgersDev& t, void* stream) {
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  hipLaunchKernelGGL((burgers_correct_kernel<D, M>), dim3(grid_for(nel, 256)), dim3(256), 0, (hipStream_t)stream, g,
+                     dt, Q, W, Qout, t);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+#define RIDG_BURGERS_CASES(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(1, 5) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 1) X(3, 2)
+
+int launch_burgers_predict(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
+                           const BurgersDev& t, int64_t nel, double* scratch, int64_t scratch_elems, int max_iter,
+                           int32_t* stats, void* stream) {
+  if (scratch_elems < 1 || max_iter < 1) return (int)hipErrorInvalidValue;
+#define RIDG_BP(DD, MM) \
+  if (d == DD && M == MM) \
+    return burgers_predict_dm<DD, MM>(g, dt, Q, W, t, nel, scratch, scratch_elems, max_iter, stats, stream);
+  RIDG_BURGERS_CASES(RIDG_BP)
+#undef RIDG_BP
+  return (int)hipErrorInvalidValue;
+}
+
+int launch_burgers_correct(int d, int M, const DevGeom& g, double dt, const double* Q, const double* W,
+                           double* Qout, const BurgersDev& t, void* stream) {
+#define RIDG_BC(DD, MM) \
+  if (d == DD && M == MM) return burgers_correct_dm<DD, MM>(g, dt, Q, W, Qout, t, stream);
+  RIDG_BURGERS_CASES(RIDG_BC)
+#undef RIDG_BC
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace ridg

@@ -70,6 +70,7 @@ struct Problem {
   int precision = 0;
   int refine = 0;
   int solver = 0;  // resolved
+  int newton_max = 0;  // RIDG_FLUX_BURGERS: Newton iterations per region at most
   int64_t nel = 0;
 };
 
@@ -326,5 +327,44 @@ int launch_predict_dense(int d, int M, const DevGeom& g, double dt, const double
 int launch_correct(int d, int M, int flux, const DevGeom& g, double dt, const double* Q, const double* W,
                    double* Qout, const DevTensors& t, void* stream);
 int launch_check_finite(const double* x, int64_t n, int32_t* flag, void* stream);
+
+// ---------------------------------------------------------------- Burgers (Newton prediction)
+// Orders the Newton path implements per dimension (region system of 3^d theta_T unknowns).
+bool burgers_supported(int d, int M);
+// Gauss-Legendre points per axis of the Burgers tables: exact for the products of a basis function
+// with F(w) = w^2 / 2 or with F'(w) and a second basis function (per-axis degree 3M - 3).
+constexpr int burgers_q(int M) { return (M + 1) > (3 * M - 1) / 2 ? (M + 1) : (3 * M - 1) / 2; }
+// Host tables (FP64) of the Newton prediction and the nonlinear correction; point sets are the tensor
+// Gauss rules on the space-time element (volume, q^(d+1) points) and on its faces (q^d points
+// (tau, xi_perp); face f = 2 i + (s > 0) lies at xi_i = s).
+struct BurgersHost {
+  int q = 0, nq = 0, nqf = 0;
+  std::vector<double> psiv;    // [l][pt]      Psi_l at the volume points
+  std::vector<double> dpsivw;  // [i][k][pt]   w_pt d_xi_i Psi_k (residual volume term)
+  std::vector<double> projw;   // [p][pt]      w_pt Psi_p / 2^(d+1) (projection onto Psi, eq. Jacproj)
+  std::vector<double> dphivw;  // [i][k][pt]   w_pt d_xi_i Phi_k (correction volume term)
+  std::vector<double> psif;    // [f][l][pf]   Psi_l at the points of face f
+  std::vector<double> psifw;   // [f][k][pf]   w_pf Psi_k on face f
+  std::vector<double> phifw;   // [f][k][pf]   w_pf Phi_k on face f
+  std::vector<int32_t> bptr;   // [i][k][l] -> first entry of (k, l) in bp / bval (size d nt^2 + 1)
+  std::vector<int32_t> bp;     // p of each non-zero beta^i_{k l p} = int d_xi_i Psi_k Psi_p Psi_l
+  std::vector<double> bval;
+  std::vector<int32_t> lift;   // [j] space-time index of spatial mode j held constant in time
+};
+int build_burgers_tables(const Problem& P, const Basis& B, BurgersHost* out, std::string* msg);
+// Device view of the same tables (pointers into the workspace).
+struct BurgersDev {
+  const double *Tt, *Cc;
+  const double *psiv, *dpsivw, *projw, *dphivw, *psif, *psifw, *phifw, *bval;
+  const int32_t *bptr, *bp, *lift;
+};
+// Newton prediction of elements [first, first + count) (one workgroup each, `scratch` holds count
+// augmented region matrices); stats: [0] max iterations, [1] failures, [2..3] total iterations (int64),
+// [4..5] region solves (int64).
+int launch_burgers_predict(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
+                           const BurgersDev& t, int64_t nel, double* scratch, int64_t scratch_elems, int max_iter,
+                           int32_t* stats, void* stream);
+int launch_burgers_correct(int d, int M, const DevGeom& g, double dt, const double* Q, const double* W,
+                           double* Qout, const BurgersDev& t, void* stream);
 
 }  // namespace ridg

@@ -230,6 +230,20 @@ def advection_3d(n=128, M=3, seed=2104, cfl=0.5, steps=20, shape=None):
                     dict(cen=cen, sig=sig))
 
 
+def burgers(d=2, n=128, M=4, cfl=0.1, steps=20):
+    """Workload: Burgers q_t + sum_i (q^2/2)_{x_i} = 0 from the initial state of eq. (burger2d), read as
+    periodic on the unit box, q0 = 2^-d prod_i (1 - cos 2 pi x_i) (values in [0, 1], so the largest
+    wave speed is 1 and dt = cfl h). Smooth until t ~ 0.245 in 2D (1/pi in 1D); at cfl = 0.1 the
+    region systems stay solvable well past t = 0.2."""
+    mesh = (n,) * d
+
+    def half_one_minus_cos(x):
+        return 0.5 * (1.0 - np.cos(2.0 * np.pi * x))
+
+    q0 = project_separable([(1.0, [half_one_minus_cos] * d)], d, mesh, M)
+    return Workload(f"{d}d-burgers", d, mesh, M, ("burgers", ()), cfl / n, steps, q0)
+
+
 def random_state(d, n, M, seed):
     """Seeded random coefficients with a decaying modal spectrum (parity inputs)."""
     rng = np.random.default_rng(seed)

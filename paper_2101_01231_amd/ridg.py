@@ -23,19 +23,21 @@ RIDG_E_SINGULAR = -4
 RIDG_E_NONFINITE = -5
 RIDG_E_UNSUPPORTED = -6
 RIDG_W_UNSTABLE = 1
+RIDG_W_NOT_CONVERGED = 2
 
-FLUX_CONST, FLUX_ROTATION, FLUX_AFFINE = 0, 1, 2
+FLUX_CONST, FLUX_ROTATION, FLUX_AFFINE, FLUX_BURGERS = 0, 1, 2, 3
 BASIS_P, BASIS_Q = 0, 1
-ABI_VERSION = 2
+ABI_VERSION = 3
 FP64, FP32_REFINE = 0, 1
-SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE = 0, 1, 2, 3
+SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE, SOLVER_NEWTON = 0, 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE, OPT_MFMA, OPT_BRICK = 1, 2, 3, 4, 5, 6
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
     "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_set_option",
-    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_advance_static", "ridg_synchronize", "ridg_destroy",
+    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_advance_static", "ridg_newton_stats", "ridg_synchronize",
+    "ridg_destroy",
     "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_host_spectral_radius",
     "ridg_error_string", "ridg_last_error",
 ]
@@ -48,7 +50,7 @@ class RidgProblem(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("basis", ctypes.c_int32),
         ("flux", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("newton_max_iter", ctypes.c_int32),
         ("velocity", ctypes.c_double * 3),
         ("rot_center", ctypes.c_double * 2),
         ("vel_grad", ctypes.c_double * 9),
@@ -125,6 +127,8 @@ def lib():
         L.ridg_autotune.argtypes = [vp, dbl, i32, ctypes.POINTER(dbl)]
         L.ridg_step_batch.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(dbl), i32, vp]
         L.ridg_advance_static.argtypes = [P, vp, vp, sz, i32, dbl, vp]
+        L.ridg_newton_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                                        ctypes.POINTER(i64), i32]
         L.ridg_synchronize.argtypes = [vp]
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
@@ -147,7 +151,7 @@ def _check(rc):
 
 
 def make_problem(dim, n, order, velocity=None, flux=FLUX_CONST, rot_center=(0.5, 0.5), vel_grad=None,
-                 precision=FP64, refine_steps=0, solver=SOLVER_AUTO, basis=BASIS_P, length=None):
+                 precision=FP64, refine_steps=0, solver=SOLVER_AUTO, basis=BASIS_P, length=None, newton_max_iter=0):
     p = RidgProblem()
     p.dim = dim
     n = tuple(n) if hasattr(n, "__len__") else (n,) * dim
@@ -156,7 +160,7 @@ def make_problem(dim, n, order, velocity=None, flux=FLUX_CONST, rot_center=(0.5,
     p.order = order
     p.basis = basis
     p.flux = flux
-    p.reserved0 = 0
+    p.newton_max_iter = newton_max_iter
     L = tuple(length or ())
     for i in range(3):
         p.length[i] = float(L[i]) if i < len(L) else 0.0
@@ -248,6 +252,7 @@ class Simulation:
         self.theta = self.info.theta
         self.theta_t = self.info.theta_t
         self.n_el = self.info.n_elements
+        self.last_warning = RIDG_OK
 
     def get_info(self):
         """Sizes, cost model and the per-dt analyses of the handle (ridg_info)."""
@@ -284,8 +289,15 @@ class Simulation:
             _check(lib().ridg_get_state(self.handle, ctypes.c_void_p(out.data_ptr()), out.numel(), DEVICE))
             return out
         a = np.empty((self.n_el, self.theta))
-        _check(lib().ridg_get_state(self.handle, a.ctypes.data, a.size, HOST))
+        self.last_warning = _check(lib().ridg_get_state(self.handle, a.ctypes.data, a.size, HOST))
         return a
+
+    def newton_stats(self, reset=False):
+        """Burgers: dict of the Newton counters since creation or the last reset (synchronises)."""
+        mx, tot, sol, fail = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ridg_newton_stats(self.handle, ctypes.byref(mx), ctypes.byref(tot), ctypes.byref(sol),
+                                       ctypes.byref(fail), 1 if reset else 0))
+        return {"max_iters": mx.value, "total_iters": tot.value, "solves": sol.value, "failures": fail.value}
 
     def get_prediction(self, dt):
         a = np.empty((self.n_el, self.theta_t))

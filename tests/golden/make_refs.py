@@ -1,7 +1,7 @@
 """Write the oracle references of the reduced-size, full-step-count parity cases.
 
 Each case runs a benchmark workload's generator at a smaller mesh for the step count of its
-configuration, through the FP64 oracle only (``oracle.scheme.step``), and stores the initial state
+configuration, through the FP64 oracle only (``oracle.scheme.step``, ``oracle.burgers.step``), and stores the initial state
 and the final state in ``tests/golden/<name>.npz``. The GPU parity tests load both and compare the
 library's result element by element. Run from the repository root:
 
@@ -19,6 +19,7 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 sys.path.insert(0, ROOT)
 
+import oracle.burgers as BG  # noqa: E402
 import oracle.scheme as S  # noqa: E402
 from paper_2101_01231_amd import inputs as I  # noqa: E402
 
@@ -31,15 +32,19 @@ CASES = {
     "adv2d32_m3_100steps": (lambda: I.advection_2d(n=32, M=3), 100),
     # a mesh the brick kernels tile (16 x 4 x 4 bricks)
     "adv3d16x8x8_m3_20steps": (lambda: I.advection_3d(M=3, shape=(16, 8, 8)), 20),
+    # Burgers (Newton prediction): the benchmark's initial state and cfl on a 12^2 mesh, to t = 1/6
+    "burgers2d12_m3_20steps": (lambda: I.burgers(d=2, n=12, M=3), 20),
 }
 
 
 def make(name):
     gen, steps = CASES[name]
     wl = gen()
-    prob = S.Problem(d=wl.d, n=wl.n, M=wl.M, velocity=wl.velocity)
     t0 = time.time()
-    ref = S.step(prob, wl.q0, wl.dt, steps)
+    if wl.velocity[0] == "burgers":
+        ref = BG.step(BG.BurgersProblem(d=wl.d, n=wl.n, M=wl.M), wl.q0, wl.dt, steps)
+    else:
+        ref = S.step(S.Problem(d=wl.d, n=wl.n, M=wl.M, velocity=wl.velocity), wl.q0, wl.dt, steps)
     path = os.path.join(HERE, name + ".npz")
     np.savez_compressed(path, q0=wl.q0, ref=ref, dt=np.float64(wl.dt), steps=np.int64(steps), d=np.int64(wl.d),
                         n=np.array(wl.n, dtype=np.int64), M=np.int64(wl.M),

@@ -192,3 +192,31 @@ def test_reduced_precision_constant_velocity_needs_brick_meshes():
         with pytest.raises(ridg.RidgError) as ei:
             ridg.workspace_bytes(p)
         assert ei.value.code == ridg.RIDG_E_UNSUPPORTED
+
+
+def test_burgers_problems_validated():
+    """RIDG_FLUX_BURGERS: Newton is its only solver, FP64 only, orders per dimension as documented,
+    newton_max_iter bounded (and refused for the linear fluxes)."""
+    ok = [(1, 5), (2, 4), (3, 2)]
+    for d, M in ok:
+        assert ridg.workspace_bytes(ridg.make_problem(d, (4,) * d, M, flux=ridg.FLUX_BURGERS)) > 0
+    bad = [
+        (dict(dim=2, n=(4, 4), order=5, flux=ridg.FLUX_BURGERS), ridg.RIDG_E_UNSUPPORTED),
+        (dict(dim=3, n=(4, 4, 4), order=3, flux=ridg.FLUX_BURGERS), ridg.RIDG_E_UNSUPPORTED),
+        (dict(dim=2, n=(4, 4), order=3, flux=ridg.FLUX_BURGERS, precision=ridg.FP32_REFINE), ridg.RIDG_E_UNSUPPORTED),
+        (dict(dim=2, n=(4, 4), order=3, flux=ridg.FLUX_BURGERS, solver=ridg.SOLVER_REGION), ridg.RIDG_E_INVAL),
+        (dict(dim=2, n=(4, 4), order=3, velocity=(1.0, 1.0), solver=ridg.SOLVER_NEWTON), ridg.RIDG_E_INVAL),
+        (dict(dim=2, n=(4, 4), order=3, flux=ridg.FLUX_BURGERS, newton_max_iter=101), ridg.RIDG_E_INVAL),
+        (dict(dim=2, n=(4, 4), order=3, flux=ridg.FLUX_BURGERS, newton_max_iter=-1), ridg.RIDG_E_INVAL),
+        (dict(dim=2, n=(4, 4), order=3, velocity=(1.0, 1.0), newton_max_iter=3), ridg.RIDG_E_INVAL),
+    ]
+    for kw, code in bad:
+        kw = dict(kw)
+        p = ridg.make_problem(kw.pop("dim"), kw.pop("n"), kw.pop("order"), **kw)
+        with pytest.raises(ridg.RidgError) as ex:
+            ridg.workspace_bytes(p)
+        assert ex.value.code == code, kw
+    # the host region-matrix inspection has no meaning for a state-dependent system
+    p = ridg.make_problem(2, (4, 4), 3, flux=ridg.FLUX_BURGERS)
+    with pytest.raises(ridg.RidgError):
+        ridg.host_region_matrix(p, 0, 0.01)
