@@ -45,7 +45,8 @@ KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
                 "fused_prefactored_kernel": ["k_prefactored.hip"], "correct_kernel": ["k_correct.hip"],
                 "predict_tear_kernel": ["k_tear_dense.hip"], "predict_dense_kernel": ["k_tear_dense.hip"],
                 "batch_predict_kernel": ["k_batch.hip"], "batch_correct_kernel": ["k_batch.hip"],
-                "tap_mfma_kernel": ["k_mfma.hip"], "brick_step_kernel": ["k_brick.hip"]}
+                "tap_mfma_kernel": ["k_mfma.hip"], "brick_step_kernel": ["k_brick.hip"],
+                "burgers_predict_kernel": ["k_burgers.hip"], "burgers_correct_kernel": ["k_burgers.hip"]}
 RECORD_TAG = "traffic-record: "
 
 
@@ -66,6 +67,8 @@ def dominant_kernel(info, opts, precision):
     """Name (as the profiler prints it) of the kernel that runs the prediction stage."""
     from paper_2101_01231_amd import ridg
     d, M = _dim_order(info)
+    if info.solver == ridg.SOLVER_NEWTON:
+        return f"ridg::burgers_predict_kernel<{d}, {M}>"
     if info.solver == ridg.SOLVER_PREFACTORED:
         if opts.get("brick") or precision == "fp32":
             return f"ridg::brick_step_kernel<{M}, {'float' if precision == 'fp32' else 'double'}>"
@@ -180,6 +183,8 @@ def workload(name):
         return I.advection_3d()
     if name == "sine":
         return I.sine_1d()
+    if name == "burgers":
+        return I.burgers(d=2, n=128, M=4)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -191,6 +196,8 @@ def make_problem(wl, precision, solver, refine):
     if wl.velocity[0] == "const":
         return ridg.make_problem(wl.d, wl.n, wl.M, velocity=wl.velocity[1], precision=prec, solver=sol,
                                  refine_steps=refine)
+    if wl.velocity[0] == "burgers":
+        return ridg.make_problem(wl.d, wl.n, wl.M, flux=ridg.FLUX_BURGERS)
     return ridg.make_problem(wl.d, wl.n, wl.M, flux=ridg.FLUX_ROTATION, rot_center=wl.velocity[1],
                              precision=prec, solver=sol, refine_steps=refine)
 
@@ -199,13 +206,17 @@ def cpu_baseline(wl, target_s, threads_limit=None, _prob=None, _label=None):
     """The oracle (plain FP64, quadrature assembly, dense LAPACK region solves) on a square
     patch of elements of the same workload; rate scaled to ST-DOF-updates/s. threads_limit caps the
     BLAS pool (1: the single-thread leg)."""
+    import oracle.burgers as BG
     import oracle.scheme as S
     try:
         from threadpoolctl import threadpool_info
         threads = max([x.get("num_threads", 1) for x in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    prob = S.Problem(d=wl.d, n=wl.n, M=wl.M, velocity=wl.velocity)
+    if wl.velocity[0] == "burgers":
+        prob, step_sampled = BG.BurgersProblem(d=wl.d, n=wl.n, M=wl.M), BG.step_sampled
+    else:
+        prob, step_sampled = S.Problem(d=wl.d, n=wl.n, M=wl.M, velocity=wl.velocity), S.step_sampled
     if threads_limit:
         from threadpoolctl import threadpool_limits
         with threadpool_limits(limits=threads_limit):
@@ -226,7 +237,7 @@ def cpu_baseline(wl, target_s, threads_limit=None, _prob=None, _label=None):
                 r //= side
             els.append(prob.linear(tuple(idx)))
         t0, c0 = time.perf_counter(), time.process_time()
-        S.step_sampled(prob, wl.q0, wl.dt, els)
+        step_sampled(prob, wl.q0, wl.dt, els)
         el = time.perf_counter() - t0
         cpu = time.process_time() - c0  # summed over the process's threads
         elapsed, done, reps = el, len(els), 1
@@ -236,7 +247,7 @@ def cpu_baseline(wl, target_s, threads_limit=None, _prob=None, _label=None):
     # a whole small mesh is timed over repeated steps (at least a second of work)
     while elapsed < 1.0:
         t0, c0 = time.perf_counter(), time.process_time()
-        S.step_sampled(prob, wl.q0, wl.dt, els)
+        step_sampled(prob, wl.q0, wl.dt, els)
         elapsed += time.perf_counter() - t0
         cpu += time.process_time() - c0
         reps += 1
@@ -266,8 +277,11 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     q0_dev = torch.from_numpy(np.ascontiguousarray(wl.q0, dtype=np.float64)).to("cuda:0")
     sim.set_state(q0_dev)
     # autotuner (native, HIP events): picks segment layout / composite stencil / fused steps; graph
-    # replay is then switched off so that the library's per-stage events cover the timed steps
-    sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
+    # replay is then switched off so that the library's per-stage events cover the timed steps. The
+    # Newton solver (Burgers) has no options.
+    newton = info.solver == ridg.SOLVER_NEWTON
+    if not newton:
+        sim.autotune(wl.dt, steps=max(4, min(steps, 10)))
     tuned = {"graph": sim.get_option(ridg.OPT_GRAPH), "fused": sim.get_option(ridg.OPT_FUSED)}
     opts = {"plan_layout": sim.get_option(ridg.OPT_PLAN_LAYOUT), "composite": sim.get_option(ridg.OPT_COMPOSITE),
             "mfma": sim.get_option(ridg.OPT_MFMA), "brick": sim.get_option(ridg.OPT_BRICK), **tuned}
@@ -287,6 +301,8 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(nlat)]
     sim.enable_timing(True)
     torch.cuda.synchronize()
+    if newton:
+        sim.newton_stats(reset=True)
     for s in range(nlat):
         starts[s].record(stream)
         sim.step(1, wl.dt)
@@ -294,6 +310,7 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     torch.cuda.synchronize()
     tim = sim.get_timing()
     sim.enable_timing(False)
+    nst = sim.newton_stats() if newton else None
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
     # throughput: the autotuned options, all timed steps in one call, from the initial state each trial
     sim.set_option(ridg.OPT_GRAPH, tuned["graph"])
@@ -317,7 +334,7 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     pred_ms = tim.predict_ms / max(tim.steps, 1)
     corr_ms = tim.correct_ms / max(tim.steps, 1)
     return dict(info=info, wall=wall, walls=walls, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q, opts=opts,
-                value=info.n_elements * info.theta_t * steps / wall)
+                value=info.n_elements * info.theta_t * steps / wall, newton=nst)
 
 
 def copy_reference(args):
@@ -405,14 +422,15 @@ def main():
     # reduced precision: FP32 region solves (variable velocity, or the REGION solver), or the 3D brick
     # kernel's FP32 matrix-core predictions (constant velocity on a brick-divisible mesh)
     brickable = wl.d == 3 and wl.M in (2, 3) and wl.n[0] % 16 == 0 and wl.n[1] % 4 == 0 and wl.n[2] % 4 == 0
-    has_fp32 = wl.velocity[0] != "const" or args.solver == "region" or (brickable and args.solver == "auto")
+    has_fp32 = (wl.velocity[0] not in ("const", "burgers") or args.solver == "region" or
+                (brickable and args.solver == "auto"))
     want = ["fp64", "fp32"] if (args.precision == "best" and has_fp32) else \
         (["fp64"] if args.precision == "best" else [args.precision])
     runs = {p: run_path(wl, p, args.solver, args.refine, args.steps, args.warmup, p, args.trials, args.latency_steps)
             for p in want}
     T = (args.warmup + args.steps) * wl.dt
     ex = None
-    if not args.no_accuracy:
+    if not args.no_accuracy and wl.exact is not None:
         ex = wl.exact(T)
         for r in runs.values():
             r["err"] = float(np.linalg.norm(r["q"] - ex) / np.linalg.norm(ex))
@@ -424,11 +442,15 @@ def main():
             best = p
     R = runs[best]
     info = R["info"]
-    achieved = info.flops_predict / (R["pred_ms"] * 1e-3) / 1e12
+    newton = info.solver == ridg.SOLVER_NEWTON
+    # Newton: the library's flop count is per iteration of every region; scale by the measured average
+    iters = R["newton"]["total_iters"] / max(R["newton"]["solves"], 1) if newton else 1.0
+    achieved = info.flops_predict * iters / (R["pred_ms"] * 1e-3) / 1e12
     peak = FP64_VECTOR_PEAK_TFLOPS if best == "fp64" else FP32_VECTOR_PEAK_TFLOPS
-    roofline = {"bound": "alu", "kernel": "prediction (region solves)", "achieved": achieved,
-                "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "flops_per_launch": info.flops_predict, "avg_launch_ms": R["pred_ms"],
+    roofline = {"bound": "alu",
+                "kernel": "prediction (Newton on every region system)" if newton else "prediction (region solves)",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "flops_per_launch": info.flops_predict * iters, "avg_launch_ms": R["pred_ms"],
                 "correction": {"achieved_tflops": info.flops_correct / (R["corr_ms"] * 1e-3) / 1e12,
                                "achieved_gbs": info.bytes_correct / (R["corr_ms"] * 1e-3) / 1e9,
                                "avg_ms": R["corr_ms"]}}
@@ -477,11 +499,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "fp64" else "f32+f64",
+        "dtype": ("f64+f32" if newton and (3 ** wl.d * info.theta_t) * (3 ** wl.d * info.theta_t + 1) * 8 > 96 * 1024
+                  else ("f64" if best == "fp64" else "f32+f64")),
         "data": "synthetic",
         "config": {"workload": wl.name, "n": list(wl.n), "order": wl.M, "theta_t": info.theta_t,
-                   "velocity": list(map(str, wl.velocity[1])), "dt": wl.dt, "cfl": 0.5,
-                   "solver": ["auto", "prefactored", "region", "dense"][info.solver], "precision": best,
+                   "velocity": list(map(str, wl.velocity[1])) if not newton else "burgers flux q^2/2",
+                   "dt": wl.dt, "cfl": 0.1 if newton else 0.5,
+                   "solver": ["auto", "prefactored", "region", "dense", "newton"][info.solver], "precision": best,
                    "options": R["opts"],
                    "refine_steps": args.refine if best == "fp32" else 0},
         "spatial_dof_updates_per_s": info.n_elements * info.theta * args.steps / R["wall"],
@@ -506,6 +530,8 @@ def main():
         print("[bench] timing the CPU oracle on one BLAS thread", file=sys.stderr, flush=True)
         one = cpu_baseline(wl, args.cpu_seconds, threads_limit=1)
         out["cpu_baseline"]["single_thread"] = {k: one[k] for k in ("value", "unit", "cores", "sample")}
+    if newton:
+        out["newton"] = {"avg_iterations": iters, **R["newton"]}
     print(json.dumps(out), flush=True)
 
 

@@ -100,7 +100,8 @@ extern "C" {
 #define RIDG_SOLVER_DENSE 3       /* per element: dense pivoted LU of the whole 3^d theta_T region system */
 #define RIDG_SOLVER_NEWTON 4      /* RIDG_FLUX_BURGERS (its only solver; AUTO selects it): one workgroup per
                                      region runs the Newton iterations, each a dense pivoted elimination of
-                                     the whole region Jacobian */
+                                     the whole region Jacobian in LDS (FP64 up to 48 KB, FP32 above; the
+                                     residual is always FP64, so the iteration converges to the FP64 root) */
 
 /* memory kinds for set/get */
 #define RIDG_HOST 0

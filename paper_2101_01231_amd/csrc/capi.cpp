@@ -42,7 +42,6 @@ int hip_fail(int err, const char* what) {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 constexpr int64_t kDenseScratchBytes = (int64_t)256 << 20;
-constexpr int64_t kNewtonScratchBytes = (int64_t)512 << 20;  // region Jacobians of one Newton launch
 
 struct Layout {
   size_t q0, q1, w, stage, tens, g, dc, kc, fg, fd, fk, fgs, taps, plans, items[kLayouts], item_plan[kLayouts], dense, scratch, flag, ptab, tplans, telems,
@@ -128,10 +127,7 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
   const int64_t N = (int64_t)std::pow(3, P.d) * nt;
   const int64_t per = N * (N + 1) * 8;
   const bool newton = P.solver == RIDG_SOLVER_NEWTON;
-  const int64_t n_scr = newton ? P.nel : n_dense;
-  L.scratch_elems =
-      n_scr > 0 ? std::max<int64_t>(1, std::min<int64_t>(n_scr, (newton ? kNewtonScratchBytes : kDenseScratchBytes) / per))
-                : 0;
+  L.scratch_elems = n_dense > 0 ? std::max<int64_t>(1, std::min<int64_t>(n_dense, kDenseScratchBytes / per)) : 0;
   L.scratch = take(std::max<int64_t>(L.scratch_elems, 1) * per);
   L.flag = take(256);
   if (newton) {  // Burgers tables: doubles, then the int32 index tables
@@ -843,8 +839,7 @@ static int run_predict(ridg_t* h, const double* Q, double dt) {
   const Problem& P = h->P;
   int err = 0;
   if (P.solver == RIDG_SOLVER_NEWTON) {
-    err = launch_burgers_predict(P.d, P.M, h->geom, dt, Q, h->W, h->bd, P.nel, h->scratch, h->L.scratch_elems,
-                                 P.newton_max, h->nstats, h->stream);
+    err = launch_burgers_predict(P.d, P.M, h->geom, dt, Q, h->W, h->bd, P.nel, P.newton_max, h->nstats, h->stream);
   } else if (P.solver == RIDG_SOLVER_PREFACTORED) {
     err = launch_predict_prefactored(P.d, P.M, h->geom, Q, h->W, h->G, h->host_taps.data(), h->ntaps, h->stream);
   } else if (P.solver == RIDG_SOLVER_REGION) {

@@ -5,18 +5,21 @@
 // LDS. Each Newton iteration
 //   1. evaluates w = Psi^T W_r at the volume and face Gauss points of every region element,
 //   2. projects F'(w) = w on the space-time basis (eq. Jacproj; quadrature once per mode),
-//   3. assembles one row of [J | R] per thread in a per-workgroup scratch matrix: time term and
+//   3. assembles one row of [J | R] per thread in the workgroup's LDS: time term and
 //      causal source from the exact tensors, volume flux residual by quadrature, volume Jacobian
 //      quasi-quadrature-free (sum_p beta^i_{k l p} F'_p with the exact triple products, eq.
 //      Jacobian2), face terms (Rusanov inside the region, own-trace physical flux on its boundary)
 //      and their Jacobian blocks by face quadrature,
-//   4. solves J delta = R by Gaussian elimination with partial pivoting and updates W <- W - delta,
+//   4. solves J delta = R by Gaussian elimination with partial pivoting in LDS (FP64 for the systems of
+//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2) and updates W <- W - delta,
 //      until max|delta| <= 1e-13 max(1, max|W|) or the iteration limit.
 // Only the centre's W is written. The Rusanov wave speed of a face is max(|mean q_a|, |mean q_b|)
 // from the two elements' states at t^n (fixed during the iteration).
 //
 // Correction: one thread per element, volume term and face fluxes by quadrature from the element's
 // own prediction and its face neighbours' predictions.
+#include <type_traits>
+
 #include "kernels_common.hpp"
 
 namespace ridg {
@@ -75,14 +78,14 @@ __device__ __noinline__ void newton_points(const BurgersDev& t, const double* s_
 // Row R = (r, k) of [J | R] (one thread): time term and causal source, volume flux residual by
 // quadrature, volume Jacobian from the triple products (eq. Jacobian2), face terms and their Jacobian
 // blocks by face quadrature.
-template <int D, int M>
-__device__ __noinline__ void newton_row(const BurgersDev& t, double c0, double c1, double c2, int R,
+template <int D, int M, class TS>
+__device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, double c1, double c2, int R,
                                         const double* s_W, const double* s_q, const double* s_wv,
-                                        const double* s_wf, const double* s_fp, double* __restrict__ row) {
+                                        const double* s_wf, const double* s_fp, TS* __restrict__ row) {
   using C = BCfg<D, M>;
   constexpr int NS = C::NS, NT = C::NT, N = C::N, LD = C::LD, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
   const int r = R / NT, k = R % NT;
-  for (int j = 0; j < LD; ++j) row[j] = 0.0;
+  for (int j = 0; j < ((LD + 3) & ~3); ++j) row[j] = (TS)0;
   double dg[NT];
   double res = 0.0;
 #pragma unroll
@@ -153,29 +156,31 @@ __device__ __noinline__ void newton_row(const BurgersDev& t, double c0, double c
     }
     if (inside) {
 #pragma unroll
-      for (int l = 0; l < NT; ++l) row[r2 * NT + l] = nb[l];
+      for (int l = 0; l < NT; ++l) row[r2 * NT + l] = (TS)nb[l];
     }
   }
 #pragma unroll
-  for (int l = 0; l < NT; ++l) row[r * NT + l] = dg[l];
-  row[N] = res;
+  for (int l = 0; l < NT; ++l) row[r * NT + l] = (TS)dg[l];
+  row[N] = (TS)res;
 }
 
-// Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A, then back
-// substitution into s_x. Pivot: the row of largest |A[r][c]|, compared on a 32-bit key (FP32 image of
-// |A[r][c]| with the low bits replaced by the row, ties to the lowest row), reduced within each
-// wavefront and then across wavefronts in LDS.
-template <int N>
-__device__ __noinline__ void newton_solve(double* __restrict__ A, double* s_x, double* s_l, double* s_piv,
-                                          int* s_key) {
-  constexpr int LD = N + 1, NW = kBurgersThreads / 64;
+// Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A held in LDS (rows
+// padded to LDP = a multiple of 4 entries), then back substitution; the solution goes to s_x in FP64.
+// Pivot: the row of largest |A[r][c]|, compared on a 32-bit key (FP32 image of |A[r][c]| with the low
+// bits replaced by the row, ties to the lowest row), reduced within each wavefront and then across
+// wavefronts. The rank-1 update runs on 4-entry chunks from the 4-aligned column at or below c:
+// entries left of c are dead (the factor L is not kept) and may take any value.
+template <int N, class TS>
+__device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv, int* s_key) {
+  constexpr int LD = N + 1, LDP = (LD + 3) & ~3, NW = kBurgersThreads / 64;
   constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : 10);
   constexpr unsigned RMASK = (1u << RB) - 1u;
+  typedef TS v4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int c = 0; c < N; ++c) {
     unsigned key = 0u;
     for (int Rr = c + tid; Rr < N; Rr += kBurgersThreads) {
-      const unsigned kk = (__float_as_uint((float)fabs(A[(size_t)Rr * LD + c])) & ~RMASK) | (RMASK - (unsigned)Rr);
+      const unsigned kk = (__float_as_uint((float)fabs((double)A[Rr * LDP + c])) & ~RMASK) | (RMASK - (unsigned)Rr);
       key = max(key, kk);
     }
     key = seg_max_pow2<64>(key);
@@ -184,55 +189,74 @@ __device__ __noinline__ void newton_solve(double* __restrict__ A, double* s_x, d
     unsigned best = 0u;
     for (int w = 0; w < NW; ++w) best = max(best, (unsigned)s_key[w]);
     const int p = (int)(RMASK - (best & RMASK));
-    for (int j = c + tid; j < LD; j += kBurgersThreads) {
-      const double vc = A[(size_t)c * LD + j], vp = A[(size_t)p * LD + j];
-      if (p != c) {
-        A[(size_t)c * LD + j] = vp;
-        A[(size_t)p * LD + j] = vc;
+    const int j0 = c & ~3;
+    for (int j = j0 + tid; j < LDP; j += kBurgersThreads) {
+      const TS vc = A[c * LDP + j], vp = A[p * LDP + j];
+      if (p != c && j >= c) {
+        A[c * LDP + j] = vp;
+        A[p * LDP + j] = vc;
       }
       s_piv[j] = vp;
     }
     __syncthreads();
-    const double inv = 1.0 / s_piv[c];
-    for (int Rr = c + 1 + tid; Rr < N; Rr += kBurgersThreads) s_l[Rr] = A[(size_t)Rr * LD + c] * inv;
+    const TS inv = (TS)1 / s_piv[c];
+    for (int Rr = c + 1 + tid; Rr < N; Rr += kBurgersThreads) s_l[Rr] = A[Rr * LDP + c] * inv;
     __syncthreads();
-    const int rows = N - c - 1, cols = LD - c - 1;
-    for (int q = tid; q < rows * cols; q += kBurgersThreads) {
-      const int Rr = c + 1 + q / cols, j = c + 1 + q % cols;
-      A[(size_t)Rr * LD + j] = fma(-s_l[Rr], s_piv[j], A[(size_t)Rr * LD + j]);
+    const int nch = (LDP - j0) >> 2, items = (N - c - 1) * nch;
+#pragma unroll 4
+    for (int q = tid; q < items; q += kBurgersThreads) {
+      const int rr = q / nch, ch = q - rr * nch;
+      const int Rr = c + 1 + rr;
+      v4* a = (v4*)(A + Rr * LDP + j0) + ch;
+      const v4 pv = *((const v4*)(s_piv + j0) + ch);
+      const TS l = s_l[Rr];
+      v4 x = *a;
+      x.x = fma(-l, pv.x, x.x);
+      x.y = fma(-l, pv.y, x.y);
+      x.z = fma(-l, pv.z, x.z);
+      x.w = fma(-l, pv.w, x.w);
+      *a = x;
     }
     __syncthreads();
   }
   for (int c = N - 1; c >= 0; --c) {
-    if (tid == 0) s_x[c] = A[(size_t)c * LD + N] / A[(size_t)c * LD + c];
+    if (tid == 0) s_x[c] = (double)A[c * LDP + N] / (double)A[c * LDP + c];
     __syncthreads();
-    const double xc = s_x[c];
-    for (int Rr = tid; Rr < c; Rr += kBurgersThreads)
-      A[(size_t)Rr * LD + N] = fma(-A[(size_t)Rr * LD + c], xc, A[(size_t)Rr * LD + N]);
+    const TS xc = (TS)s_x[c];
+    for (int Rr = tid; Rr < c; Rr += kBurgersThreads) A[Rr * LDP + N] = fma(-A[Rr * LDP + c], xc, A[Rr * LDP + N]);
     __syncthreads();
   }
 }
+
+// Arithmetic of the region Jacobian's elimination: FP64 for the small systems (up to 48 KB), FP32
+// otherwise, which halves the LDS of a workgroup and so raises the workgroups resident per CU (the
+// residual stays FP64, so Newton converges to the same FP64 root; an FP32 step only makes the
+// convergence linear with a rate of about the FP32 rounding times the condition number).
+template <int N>
+using NewtonScalar =
+    typename std::conditional<(size_t)N * ((N + 4) & ~3) * 8 <= 48 * 1024, double, float>::type;
 
 template <int D, int M>
 __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeom g, double dt,
                                                                           const double* __restrict__ Qs,
                                                                           double* __restrict__ W, BurgersDev t,
-                                                                          int64_t first, int64_t nel,
-                                                                          double* __restrict__ scratch, int max_iter,
+                                                                          int64_t first, int64_t nel, int max_iter,
                                                                           int32_t* __restrict__ stats) {
   using C = BCfg<D, M>;
   constexpr int NS = C::NS, NT = C::NT, NB = C::NB, N = C::N, LD = C::LD, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
   const int64_t e = first + blockIdx.x;
   if (e >= nel) return;
-  double* A = scratch + (size_t)blockIdx.x * N * LD;  // [N][N + 1]: Jacobian | residual
+  using TS = NewtonScalar<N>;
+  constexpr int LDP = (LD + 3) & ~3;
+  __shared__ __align__(16) TS s_A[N * LDP];  // [N][LDP]: Jacobian | residual | padding
   __shared__ double s_W[N];
   __shared__ double s_q[NB * NS];
   __shared__ double s_wv[NB * NQ];
   __shared__ double s_wf[NB * NF * NQF];
   __shared__ double s_fp[NB * NT];
   __shared__ double s_x[N];
-  __shared__ double s_l[N];
-  __shared__ double s_piv[LD];
+  __shared__ __align__(16) TS s_piv[LDP];
+  __shared__ TS s_l[N];
   __shared__ int s_key[kBurgersThreads / 64];
   __shared__ double s_red[2][kBurgersThreads / 64];
   __shared__ int64_t s_ge[NB];
@@ -267,9 +291,9 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
     ++it;
     newton_points<D, M>(t, s_W, s_wv, s_wf, s_fp);
     for (int R = tid; R < N; R += kBurgersThreads)
-      newton_row<D, M>(t, c0, c1, c2, R, s_W, s_q, s_wv, s_wf, s_fp, A + (size_t)R * LD);
+      newton_row<D, M, TS>(t, c0, c1, c2, R, s_W, s_q, s_wv, s_wf, s_fp, s_A + R * LDP);
     __syncthreads();
-    newton_solve<N>(A, s_x, s_l, s_piv, s_key);
+    newton_solve<N, TS>(s_A, s_x, s_l, s_piv, s_key);
     // update and convergence test (uniform across the workgroup)
     double md = 0.0, mw = 0.0;
     for (int x = tid; x < N; x += kBurgersThreads) {
@@ -367,11 +391,12 @@ namespace {
 
 template <int D, int M>
 int burgers_predict_dm(const DevGeom& g, double dt, const double* Q, double* W, const BurgersDev& t, int64_t nel,
-                       double* scratch, int64_t scratch_elems, int max_iter, int32_t* stats, void* stream) {
-  for (int64_t first = 0; first < nel; first += scratch_elems) {
-    const int64_t chunk = (nel - first < scratch_elems) ? nel - first : scratch_elems;
+                       int max_iter, int32_t* stats, void* stream) {
+  constexpr int64_t kChunk = (int64_t)1 << 30;  // workgroups per launch at most
+  for (int64_t first = 0; first < nel; first += kChunk) {
+    const int64_t chunk = (nel - first < kChunk) ? nel - first : kChunk;
     hipLaunchKernelGGL((burgers_predict_kernel<D, M>), dim3((unsigned)chunk), dim3(kBurgersThreads), 0,
-                       (hipStream_t)stream, g, dt, Q, W, t, first, nel, scratch, max_iter, stats);
+                       (hipStream_t)stream, g, dt, Q, W, t, first, nel, max_iter, stats);
     const int err = (int)hipGetLastError();
     if (err) return err;
   }
@@ -392,12 +417,10 @@ int burgers_correct_dm(const DevGeom& g, double dt, const double* Q, const doubl
 #define RIDG_BURGERS_CASES(X) X(1, 1) X(1, 2) X(1, 3) X(1, 4) X(1, 5) X(2, 1) X(2, 2) X(2, 3) X(2, 4) X(3, 1) X(3, 2)
 
 int launch_burgers_predict(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
-                           const BurgersDev& t, int64_t nel, double* scratch, int64_t scratch_elems, int max_iter,
-                           int32_t* stats, void* stream) {
-  if (scratch_elems < 1 || max_iter < 1) return (int)hipErrorInvalidValue;
+                           const BurgersDev& t, int64_t nel, int max_iter, int32_t* stats, void* stream) {
+  if (max_iter < 1) return (int)hipErrorInvalidValue;
 #define RIDG_BP(DD, MM) \
-  if (d == DD && M == MM) \
-    return burgers_predict_dm<DD, MM>(g, dt, Q, W, t, nel, scratch, scratch_elems, max_iter, stats, stream);
+  if (d == DD && M == MM) return burgers_predict_dm<DD, MM>(g, dt, Q, W, t, nel, max_iter, stats, stream);
   RIDG_BURGERS_CASES(RIDG_BP)
 #undef RIDG_BP
   return (int)hipErrorInvalidValue;

@@ -358,12 +358,10 @@ struct BurgersDev {
   const double *psiv, *dpsivw, *projw, *dphivw, *psif, *psifw, *phifw, *bval;
   const int32_t *bptr, *bp, *lift;
 };
-// Newton prediction of elements [first, first + count) (one workgroup each, `scratch` holds count
-// augmented region matrices); stats: [0] max iterations, [1] failures, [2..3] total iterations (int64),
-// [4..5] region solves (int64).
+// Newton prediction of every element (one workgroup per region, the region Jacobian in LDS); stats:
+// [0] max iterations, [1] failures, [2..3] total iterations (int64), [4..5] region solves (int64).
 int launch_burgers_predict(int d, int M, const DevGeom& g, double dt, const double* Q, double* W,
-                           const BurgersDev& t, int64_t nel, double* scratch, int64_t scratch_elems, int max_iter,
-                           int32_t* stats, void* stream);
+                           const BurgersDev& t, int64_t nel, int max_iter, int32_t* stats, void* stream);
 int launch_burgers_correct(int d, int M, const DevGeom& g, double dt, const double* Q, const double* W,
                            double* Qout, const BurgersDev& t, void* stream);
 

@@ -241,7 +241,38 @@ def burgers(d=2, n=128, M=4, cfl=0.1, steps=20):
         return 0.5 * (1.0 - np.cos(2.0 * np.pi * x))
 
     q0 = project_separable([(1.0, [half_one_minus_cos] * d)], d, mesh, M)
-    return Workload(f"{d}d-burgers", d, mesh, M, ("burgers", ()), cfl / n, steps, q0)
+
+    def q0_at(X):
+        v = np.ones(X.shape[1:])
+        for i in range(d):
+            v = v * half_one_minus_cos(X[i])
+        return v
+
+    def grad_sum(X):  # sum_i d q0 / d x_i
+        tot = np.zeros(X.shape[1:])
+        for i in range(d):
+            g = np.pi * np.sin(2.0 * np.pi * X[i])
+            for j in range(d):
+                if j != i:
+                    g = g * half_one_minus_cos(X[j])
+            tot = tot + g
+        return tot
+
+    def ex(t):
+        """Projection of the exact pre-shock solution: q = q0(x - q t (1,..,1)) at every quadrature
+        point (characteristics), solved by Newton's method."""
+        def f(X):
+            q = q0_at(X)
+            for _ in range(100):
+                Y = X - t * q[None]
+                upd = (q - q0_at(Y)) / (1.0 + t * grad_sum(Y))
+                q = q - upd
+                if np.max(np.abs(upd)) < 1e-15:
+                    break
+            return q
+        return project_tensor(f, d, mesh, M)
+
+    return Workload(f"{d}d-burgers", d, mesh, M, ("burgers", ()), cfl / n, steps, q0, ex)
 
 
 def random_state(d, n, M, seed):
