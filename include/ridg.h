@@ -282,6 +282,24 @@ int ridg_advance_static(const ridg_problem* problem, const double* q_in, double*
 int ridg_newton_stats(ridg_t* h, int32_t* max_iters, int64_t* total_iters, int64_t* solves, int64_t* failures,
                       int32_t reset);
 
+/* Assembly of the Newton Jacobian's volume flux block (Sec. 3: eq. Jacobian by quadrature, eq. Jacproj
+ * and eq. Jacobian2 quasi-quadrature-free, and the perturbation method), for the Burgers flux
+ * F(w) = w^2 / 2 on every axis, on n_elements space-time elements of dimension dim + 1 (orders 1..6,
+ * total-degree basis, theta_T = C(order + dim, dim + 1)): J_kl = -c int int sum_i d_xi_i Psi_k F'(w)
+ * Psi_l with c = dt / h on every axis. method: RIDG_ASM_QUADRATURE (every entry by tensor Gauss
+ * quadrature), RIDG_ASM_QQF (F'(w) projected on the space-time basis by quadrature, then contracted with
+ * the exact triple products), RIDG_ASM_PERTURBATION (central differences of the residual volume term,
+ * eps = 1e-3, one pair of residual evaluations per unknown). w: device array [n_elements][theta_T]
+ * (coefficients of each element's iterate); jac: device array [n_elements][theta_T][theta_T] (row = test
+ * function k). Queued on hip_stream. The first call for a (device, dim, order) builds the point and
+ * triple-product tables on the host and keeps a device copy until the process ends. Used to compare
+ * the three assembly costs; the Burgers solver itself assembles quasi-quadrature-free. */
+#define RIDG_ASM_QUADRATURE 0
+#define RIDG_ASM_QQF 1
+#define RIDG_ASM_PERTURBATION 2
+int ridg_assemble_jacobian(int32_t method, int32_t dim, int32_t order, const double* w, int64_t n_elements,
+                           double dt_over_h, double* jac, void* hip_stream);
+
 /* Wait for all queued work of the handle. */
 int ridg_synchronize(ridg_t* h);
 

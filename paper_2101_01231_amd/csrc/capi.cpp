@@ -11,9 +11,9 @@
 #include <string>
 #include <utility>
 #include <array>
+#include <mutex>
 #include <cstdlib>
 #include <map>
-#include <mutex>
 
 #include "ridg_internal.hpp"
 
@@ -1388,3 +1388,80 @@ int ridg_host_prediction_operator(const ridg_problem* problem, double dt, double
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- Jacobian assembly comparison (Sec. 3)
+namespace {
+struct AsmEntry {
+  int dev, d, M;
+  void* mem;  // one device block: doubles (psiv, projw, dsum, bval) then int32 (rptr, bp)
+  AsmDev view;
+};
+std::mutex g_asm_mu;
+std::vector<AsmEntry> g_asm;  // device tables per (device, dim, order), kept until the process ends
+
+int asm_tables(int d, int M, AsmDev* out) {
+  int dev = 0;
+  int err = hipGetDevice(&dev);
+  if (err) return hip_fail(err, "hipGetDevice");
+  std::lock_guard<std::mutex> lk(g_asm_mu);
+  for (const AsmEntry& a : g_asm)
+    if (a.dev == dev && a.d == d && a.M == M) {
+      *out = a.view;
+      return RIDG_OK;
+    }
+  AsmHost H;
+  std::string msg;
+  int rc = build_assembly_tables(d, M, &H, &msg);
+  if (rc) return fail(rc, msg);
+  const size_t nd = H.psiv.size() + H.projw.size() + H.dsum.size() + H.bval.size();
+  const size_t ni = H.rptr.size() + H.bp.size();
+  void* mem = nullptr;
+  err = hipMalloc(&mem, nd * 8 + ni * 4);
+  if (err) return hip_fail(err, "hipMalloc of the assembly tables");
+  std::vector<char> buf(nd * 8 + ni * 4);
+  AsmDev v{};
+  v.nt = H.nt;
+  v.nq = H.nq;
+  size_t off = 0;
+  auto putd = [&](const std::vector<double>& x) {
+    std::memcpy(buf.data() + off, x.data(), x.size() * 8);
+    const double* at = (const double*)((char*)mem + off);
+    off += x.size() * 8;
+    return at;
+  };
+  auto puti = [&](const std::vector<int32_t>& x) {
+    std::memcpy(buf.data() + off, x.data(), x.size() * 4);
+    const int32_t* at = (const int32_t*)((char*)mem + off);
+    off += x.size() * 4;
+    return at;
+  };
+  v.psiv = putd(H.psiv);
+  v.projw = putd(H.projw);
+  v.dsum = putd(H.dsum);
+  v.bval = putd(H.bval);
+  v.rptr = puti(H.rptr);
+  v.bp = puti(H.bp);
+  err = hipMemcpy(mem, buf.data(), buf.size(), hipMemcpyHostToDevice);
+  if (err) {
+    (void)hipFree(mem);
+    return hip_fail(err, "upload of the assembly tables");
+  }
+  g_asm.push_back({dev, d, M, mem, v});
+  *out = v;
+  return RIDG_OK;
+}
+}  // namespace
+
+extern "C" int ridg_assemble_jacobian(int32_t method, int32_t dim, int32_t order, const double* w, int64_t n_elements,
+                                      double dt_over_h, double* jac, void* hip_stream) {
+  if (method < RIDG_ASM_QUADRATURE || method > RIDG_ASM_PERTURBATION) return fail(RIDG_E_INVAL, "unknown method");
+  if (dim < 1 || dim > 3 || order < 1 || order > 6) return fail(RIDG_E_INVAL, "dim must be 1..3 and order 1..6");
+  if (n_elements < 0 || n_elements > ((int64_t)1 << 31)) return fail(RIDG_E_INVAL, "n_elements out of range");
+  if (n_elements > 0 && (!w || !jac)) return fail(RIDG_E_INVAL, "NULL array");
+  if (!std::isfinite(dt_over_h)) return fail(RIDG_E_INVAL, "dt_over_h not finite");
+  AsmDev t{};
+  int rc = asm_tables(dim, order, &t);
+  if (rc) return rc;
+  int err = launch_assembly(method, t, n_elements, w, dt_over_h, jac, hip_stream);
+  return err ? hip_fail(err, "assembly launch") : RIDG_OK;
+}

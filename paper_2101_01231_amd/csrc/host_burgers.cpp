@@ -190,3 +190,75 @@ int build_burgers_tables(const Problem& P, const Basis& B, BurgersHost* out, std
 }
 
 }  // namespace ridg
+
+namespace ridg {
+
+// Tables of the Jacobian-assembly comparison (any dimension, orders 1..6): the same point sets and
+// exact triple products as the Burgers tables, with the directions summed (uniform dt / h).
+int build_assembly_tables(int d, int M, AsmHost* out, std::string* msg) {
+  if (d < 1 || d > 3 || M < 1 || M > 6) {
+    *msg = "assembly comparison: dim 1..3, order 1..6";
+    return RIDG_E_INVAL;
+  }
+  const Basis B = make_basis(d, M);
+  const int nt = B.theta_t, nv = d + 1;
+  AsmHost& H = *out;
+  H.nt = nt;
+  H.q = burgers_q(M);
+  std::vector<double> gx, gw;
+  gauss_rule(H.q, &gx, &gw);
+  H.nq = 1;
+  for (int a = 0; a < nv; ++a) H.nq *= H.q;
+  const double pscale = std::ldexp(1.0, -(d + 1));
+  H.psiv.assign((size_t)nt * H.nq, 0.0);
+  H.projw.assign((size_t)nt * H.nq, 0.0);
+  H.dsum.assign((size_t)nt * H.nq, 0.0);
+  for (int pt = 0; pt < H.nq; ++pt) {
+    double x[4], wt = 1.0;
+    int c = pt;
+    for (int a = 0; a < nv; ++a) {
+      x[a] = gx[c % H.q];
+      wt *= gw[c % H.q];
+      c /= H.q;
+    }
+    for (int l = 0; l < nt; ++l) {
+      const auto& b = B.tidx[l];
+      double v = 1.0, dv = 0.0;
+      for (int a = 0; a < nv; ++a) v *= psi(b[a], x[a]);
+      for (int i = 0; i < d; ++i) {
+        double t = 1.0;
+        for (int a = 0; a < nv; ++a) t *= (a == i + 1) ? dpsi(b[a], x[a]) : psi(b[a], x[a]);
+        dv += t;
+      }
+      H.psiv[(size_t)l * H.nq + pt] = v;
+      H.projw[(size_t)l * H.nq + pt] = wt * v * pscale;
+      H.dsum[(size_t)l * H.nq + pt] = wt * dv;
+    }
+  }
+  H.rptr.assign((size_t)nt * nt + 1, 0);
+  H.bp.clear();
+  H.bval.clear();
+  for (int k = 0; k < nt; ++k)
+    for (int l = 0; l < nt; ++l) {
+      H.rptr[(size_t)k * nt + l] = (int32_t)H.bp.size();
+      for (int p = 0; p < nt; ++p) {
+        double sum = 0.0;
+        for (int i = 0; i < d; ++i) {
+          double v = 1.0;
+          for (int a = 0; a < nv && v != 0.0; ++a) {
+            const int kk = B.tidx[k][a], pp = B.tidx[p][a], ll = B.tidx[l][a];
+            v *= (a == i + 1) ? leg_d3(kk, pp, ll) : leg_t3(kk, pp, ll);
+          }
+          sum += v;
+        }
+        if (std::fabs(sum) > 1e-13) {
+          H.bp.push_back(p);
+          H.bval.push_back(sum);
+        }
+      }
+    }
+  H.rptr[(size_t)nt * nt] = (int32_t)H.bp.size();
+  return RIDG_OK;
+}
+
+}  // namespace ridg

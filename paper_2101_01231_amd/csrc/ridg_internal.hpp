@@ -365,4 +365,28 @@ int launch_burgers_predict(int d, int M, const DevGeom& g, double dt, const doub
 int launch_burgers_correct(int d, int M, const DevGeom& g, double dt, const double* Q, const double* W,
                            double* Qout, const BurgersDev& t, void* stream);
 
+// ---------------------------------------------------------------- Jacobian assembly comparison (Sec. 3)
+// Volume block J_kl = -c int int sum_i d_xi_i Psi_k F'(w) Psi_l of the Burgers flux (F'(w) = w) on
+// the space-time element, c = dt / h on every axis, by quadrature, by quasi-quadrature-free projection
+// (F'(w) projected on Psi, then the exact triple products summed over the directions), or by central
+// differences of the residual volume term, one column per unknown.
+struct AsmHost {
+  int nt = 0, q = 0, nq = 0;
+  std::vector<double> psiv;   // [l][pt] Psi_l at the volume points
+  std::vector<double> projw;  // [p][pt] w_pt Psi_p / 2^(d+1)
+  std::vector<double> dsum;   // [k][pt] w_pt sum_i d_xi_i Psi_k
+  std::vector<int32_t> rptr;  // [k][l] -> first entry in bp / bval (size nt^2 + 1)
+  std::vector<int32_t> bp;    // p of each non-zero sum_i beta^i_{k l p}
+  std::vector<double> bval;
+};
+int build_assembly_tables(int d, int M, AsmHost* out, std::string* msg);
+struct AsmDev {
+  int nt, nq;
+  const double *psiv, *projw, *dsum, *bval;
+  const int32_t *rptr, *bp;
+};
+constexpr int kAsmQuadrature = 0, kAsmQqf = 1, kAsmPerturbation = 2;
+int launch_assembly(int method, const AsmDev& t, int64_t n_elements, const double* W, double c, double* J,
+                    void* stream);
+
 }  // namespace ridg

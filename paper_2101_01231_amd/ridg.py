@@ -32,11 +32,12 @@ FP64, FP32_REFINE = 0, 1
 SOLVER_AUTO, SOLVER_PREFACTORED, SOLVER_REGION, SOLVER_DENSE, SOLVER_NEWTON = 0, 1, 2, 3, 4
 HOST, DEVICE = 0, 1
 OPT_GRAPH, OPT_PLAN_LAYOUT, OPT_FUSED, OPT_COMPOSITE, OPT_MFMA, OPT_BRICK = 1, 2, 3, 4, 5, 6
+ASM_QUADRATURE, ASM_QQF, ASM_PERTURBATION = 0, 1, 2
 
 EXPORTS = [
     "ridg_workspace_bytes", "ridg_create", "ridg_set_state", "ridg_step", "ridg_get_state",
     "ridg_get_prediction", "ridg_get_info", "ridg_enable_timing", "ridg_get_timing", "ridg_set_option",
-    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_advance_static", "ridg_newton_stats", "ridg_synchronize",
+    "ridg_get_option", "ridg_autotune", "ridg_step_batch", "ridg_advance_static", "ridg_newton_stats", "ridg_assemble_jacobian", "ridg_synchronize",
     "ridg_destroy",
     "ridg_host_region_matrix", "ridg_host_prediction_operator", "ridg_host_spectral_radius",
     "ridg_error_string", "ridg_last_error",
@@ -129,6 +130,7 @@ def lib():
         L.ridg_advance_static.argtypes = [P, vp, vp, sz, i32, dbl, vp]
         L.ridg_newton_stats.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64),
                                         ctypes.POINTER(i64), i32]
+        L.ridg_assemble_jacobian.argtypes = [i32, i32, i32, vp, i64, dbl, vp, vp]
         L.ridg_synchronize.argtypes = [vp]
         L.ridg_destroy.argtypes = [vp]
         L.ridg_host_region_matrix.argtypes = [P, i64, dbl, vp, sz]
@@ -176,6 +178,21 @@ def make_problem(dim, n, order, velocity=None, flux=FLUX_CONST, rot_center=(0.5,
     p.solver = solver
     p.reserved = 0
     return p
+
+
+def assemble_jacobian(method, dim, order, w, dt_over_h, out=None, stream=None):
+    """Volume Jacobian blocks of the Burgers flux on every element of w (a CUDA tensor
+    [n_elements, theta_T], float64) by quadrature, QQF or perturbation (ridg_assemble_jacobian)."""
+    import torch
+    n, nt = w.shape
+    if out is None:
+        out = torch.empty((n, nt, nt), dtype=torch.float64, device=w.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(w.device)
+    _check(lib().ridg_assemble_jacobian(int(method), int(dim), int(order), ctypes.c_void_p(w.data_ptr()), int(n),
+                                        float(dt_over_h), ctypes.c_void_p(out.data_ptr()),
+                                        ctypes.c_void_p(stream.cuda_stream)))
+    return out
 
 
 def workspace_bytes(problem):
