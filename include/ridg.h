@@ -80,8 +80,11 @@ extern "C" {
 
 /* basis families (Sec. 2.1) */
 #define RIDG_BASIS_P 0 /* total degree <= order-1 in space and in space-time */
-#define RIDG_BASIS_Q 1 /* tensor degree <= order-1 per variable (the paper's space); not implemented:
-                          RIDG_E_UNSUPPORTED */
+#define RIDG_BASIS_Q 1 /* tensor degree <= order-1 per variable (the paper's space, Sec. 2.1-2.2): theta =
+                          order^d, theta_T = order^(d+1), same mode ordering rule. Constant velocity, FP64,
+                          1D (orders 1-12) and 2D (orders 1-5); the step runs as the composite stencil
+                          (RIDG_OPT_COMPOSITE is always on, the other options and ridg_get_prediction,
+                          ridg_step_batch, ridg_autotune and ridg_advance_static give RIDG_E_UNSUPPORTED) */
 
 /* arithmetic of the prediction (the correction is always FP64) */
 #define RIDG_FP64 0
@@ -110,8 +113,8 @@ extern "C" {
 typedef struct ridg_problem {
   int32_t dim;          /* d in {1, 2, 3} */
   int32_t n[3];         /* elements per axis, n[i] >= 3 for i < dim (the 3^d region elements are distinct) */
-  int32_t order;        /* M >= 1: basis of total degree M-1; the library implements M <= 5 */
-  int32_t basis;        /* RIDG_BASIS_P (RIDG_BASIS_Q gives RIDG_E_UNSUPPORTED) */
+  int32_t order;        /* M >= 1: basis of degree M-1; the library implements M <= 5 (tensor basis in 1D: M <= 12) */
+  int32_t basis;        /* RIDG_BASIS_P (default) or RIDG_BASIS_Q */
   int32_t flux;         /* RIDG_FLUX_* */
   int32_t newton_max_iter; /* RIDG_FLUX_BURGERS: Newton iterations per region at most (0: 20; <= 100);
                               must be 0 for the linear fluxes */

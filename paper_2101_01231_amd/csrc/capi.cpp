@@ -133,7 +133,7 @@ Layout make_layout(const Problem& P, const RefTensors& T, const RegionPlans* R, 
   if (newton) {  // Burgers tables: doubles, then the int32 index tables
     BurgersHost H;
     std::string m;
-    if (build_burgers_tables(P, make_basis(P.d, P.M), &H, &m) == RIDG_OK) {
+    if (build_burgers_tables(P, make_basis(P.d, P.M, P.basis), &H, &m) == RIDG_OK) {
       L.btab_doubles = H.psiv.size() + H.dpsivw.size() + H.projw.size() + H.dphivw.size() + H.psif.size() +
                        H.psifw.size() + H.phifw.size() + H.bval.size();
       L.bint_ints = H.bptr.size() + H.bp.size() + H.lift.size();
@@ -354,7 +354,7 @@ int ridg_workspace_bytes(const ridg_problem* problem, size_t* bytes) {
   std::string msg;
   int rc = resolve_problem(problem, &P, &msg);
   if (rc) return fail(rc, msg);
-  Basis B = make_basis(P.d, P.M);
+  Basis B = make_basis(P.d, P.M, P.basis);
   RefTensors T = make_tensors(B);
   int64_t n_items[kLayouts] = {};
   RegionPlans R;
@@ -381,7 +381,7 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   ridg_handle* h = new (std::nothrow) ridg_handle();
   if (!h) return fail(RIDG_E_NOMEM, "host allocation failed");
   h->P = P;
-  h->B = make_basis(P.d, P.M);
+  h->B = make_basis(P.d, P.M, P.basis);
   h->T = make_tensors(h->B);
   RegionPlans R;
   std::vector<int32_t> items[kLayouts], item_plan[kLayouts];
@@ -556,7 +556,8 @@ int ridg_create(const ridg_problem* problem, void* d_workspace, size_t ws_bytes,
   h->cur = 0;
   ridg_info& I = h->info;
   I.abi_version = RIDG_ABI_VERSION;
-  I.basis = RIDG_BASIS_P;
+  I.basis = P.basis;
+  if (P.basis == RIDG_BASIS_Q) h->opt_composite = 1;  // the tensor basis runs the composite stencil only
   I.theta = T.ns;
   I.theta_t = T.nt;
   I.solver = P.solver;
@@ -896,7 +897,11 @@ static int direct_step(ridg_t* h, double dt) {
     h->cur ^= 1;
     return RIDG_OK;
   }
-  if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
+  if (pref && h->opt_composite && P.basis == RIDG_BASIS_Q) {
+    int err = launch_tap_composite_ns(P.d, h->T.ns, h->geom, h->Q[h->cur], h->Q[1 - h->cur], h->Kc,
+                                      h->host_ktaps.data(), nk, h->stream);
+    if (err) return hip_fail(err, "composite launch");
+  } else if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
     int err = mfma ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
                                             h->Q[1 - h->cur], h->Fk, h->host_ktaps.data(), nk, h->stream)
                           : launch_tap_update(P.d, P.M, 1, h->geom, h->Q[h->cur], h->Q[h->cur], h->Q[1 - h->cur],
@@ -1021,7 +1026,7 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
   for (int i = 0; i < count; ++i) {
     ridg_t* h = handles[i];
     if (!h) return fail(RIDG_E_INVAL, "NULL handle in the batch");
-    if (h->P.solver != RIDG_SOLVER_PREFACTORED || h->P.precision != RIDG_FP64)
+    if (h->P.solver != RIDG_SOLVER_PREFACTORED || h->P.precision != RIDG_FP64 || h->P.basis != RIDG_BASIS_P)
       return fail(RIDG_E_UNSUPPORTED, "batched steps need FP64 PREFACTORED handles");
     if (!(dts[i] > 0.0) || !std::isfinite(dts[i])) return fail(RIDG_E_INVAL, "dt must be positive and finite");
     for (int j = 0; j < i; ++j)
@@ -1127,6 +1132,8 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (value < 0 || value > vmax) return fail(RIDG_E_INVAL, "option value out of range");
   if (h->P.solver == RIDG_SOLVER_NEWTON && value)
     return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no execution options");
+  if (h->P.basis == RIDG_BASIS_Q && option != RIDG_OPT_GRAPH && value != (option == RIDG_OPT_COMPOSITE ? 1 : 0))
+    return fail(RIDG_E_UNSUPPORTED, "the tensor basis runs the composite stencil (RIDG_OPT_COMPOSITE = 1) only");
   int err = hipStreamSynchronize(h->stream);
   if (err) return hip_fail(err, "hipStreamSynchronize");
   switch (option) {
@@ -1187,6 +1194,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be positive and finite");
   if (h->timing) return fail(RIDG_E_INVAL, "switch stage timing off before autotuning");
   if (h->P.solver == RIDG_SOLVER_NEWTON) return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no options to tune");
+  if (h->P.basis == RIDG_BASIS_Q) return fail(RIDG_E_UNSUPPORTED, "the tensor basis has no options to tune");
   const std::string key = tune_key(h, steps);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1306,6 +1314,8 @@ int ridg_get_prediction(ridg_t* h, double dt, double* w, size_t count, int32_t w
   if (where != RIDG_HOST && where != RIDG_DEVICE) return fail(RIDG_E_INVAL, "where must be RIDG_HOST or RIDG_DEVICE");
   if (h->P.solver == RIDG_SOLVER_REGION && h->P.d == 3 && h->T.nt > 64)
     return fail(RIDG_E_UNSUPPORTED, "REGION solver supports theta_T <= 64");
+  if (h->P.basis == RIDG_BASIS_Q)
+    return fail(RIDG_E_UNSUPPORTED, "the tensor basis runs the composite stencil, which stores no predictions");
   int rc = ensure_dt_tables(h, dt);
   if (rc) return rc;
   rc = run_predict(h, h->Q[h->cur], dt);
@@ -1327,7 +1337,7 @@ int ridg_host_region_matrix(const ridg_problem* problem, int64_t element, double
   if (!a) return fail(RIDG_E_INVAL, "a is NULL");
   if (element < 0 || element >= P.nel) return fail(RIDG_E_INVAL, "element out of range");
   if (!std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt not finite");
-  Basis B = make_basis(P.d, P.M);
+  Basis B = make_basis(P.d, P.M, P.basis);
   RefTensors T = make_tensors(B);
   auto offs = region_offsets(P.d);
   const size_t n = offs.size() * T.nt;
@@ -1348,7 +1358,7 @@ int ridg_host_spectral_radius(const ridg_problem* problem, double dt, int32_t nk
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be finite and >= 0");
   if (nk < 2 || nk > 4096 || std::pow((double)nk, P.d) > (double)(1 << 22))
     return fail(RIDG_E_INVAL, "nk must be in 2..4096 with at most 2^22 grid points");
-  Basis B = make_basis(P.d, P.M);
+  Basis B = make_basis(P.d, P.M, P.basis);
   RefTensors T = make_tensors(B);
   Prefactored pf;
   rc = build_prefactored(P, T, dt, &pf, &msg);
@@ -1368,7 +1378,7 @@ int ridg_host_prediction_operator(const ridg_problem* problem, double dt, double
   if (P.flux != RIDG_FLUX_CONST) return fail(RIDG_E_INVAL, "prediction operator needs a constant velocity");
   if (!g) return fail(RIDG_E_INVAL, "g is NULL");
   if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(RIDG_E_INVAL, "dt must be finite and >= 0");
-  Basis B = make_basis(P.d, P.M);
+  Basis B = make_basis(P.d, P.M, P.basis);
   RefTensors T = make_tensors(B);
   auto offs = region_offsets(P.d);
   const size_t nb = offs.size(), cols = nb * T.ns;

@@ -14,7 +14,7 @@
 namespace ridg {
 
 // ---------------------------------------------------------------- basis
-static std::vector<std::array<int, 4>> graded_indices(int nvar, int M) {
+static std::vector<std::array<int, 4>> graded_indices(int nvar, int M, bool tensor) {
   std::vector<std::array<int, 4>> out;
   int e[4] = {0, 0, 0, 0};
   // enumerate all tuples in [0, M)^nvar with sum <= M-1
@@ -27,7 +27,7 @@ static std::vector<std::array<int, 4>> graded_indices(int nvar, int M) {
       c /= M;
       s += e[i];
     }
-    if (s > M - 1) continue;
+    if (!tensor && s > M - 1) continue;  // total degree <= M - 1 (P); tensor degree <= M - 1 per variable (Q)
     out.push_back({e[0], e[1], e[2], e[3]});
   }
   std::sort(out.begin(), out.end(), [nvar](const std::array<int, 4>& x, const std::array<int, 4>& y) {
@@ -44,12 +44,13 @@ static std::vector<std::array<int, 4>> graded_indices(int nvar, int M) {
   return out;
 }
 
-Basis make_basis(int d, int M) {
+Basis make_basis(int d, int M, int family) {
   Basis b;
   b.d = d;
   b.M = M;
-  b.sidx = graded_indices(d, M);
-  b.tidx = graded_indices(d + 1, M);
+  b.family = family;
+  b.sidx = graded_indices(d, M, family == RIDG_BASIS_Q);
+  b.tidx = graded_indices(d + 1, M, family == RIDG_BASIS_Q);
   b.theta = (int)b.sidx.size();
   b.theta_t = (int)b.tidx.size();
   return b;
@@ -234,14 +235,11 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     *msg = "dim must be 1, 2 or 3";
     return RIDG_E_INVAL;
   }
-  if (p->basis == RIDG_BASIS_Q) {
-    *msg = "the tensor (Q) basis is not implemented";
-    return RIDG_E_UNSUPPORTED;
-  }
-  if (p->basis != RIDG_BASIS_P) {
+  if (p->basis != RIDG_BASIS_P && p->basis != RIDG_BASIS_Q) {
     *msg = "unknown basis";
     return RIDG_E_INVAL;
   }
+  P.basis = p->basis;
   P.nel = 1;
   for (int i = 0; i < 3; ++i) {
     if (i < P.d) {
@@ -277,8 +275,10 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
     *msg = "order must be >= 1";
     return RIDG_E_INVAL;
   }
-  if (P.M > kMaxOrder) {
-    *msg = "order above 5 is not implemented";
+  const int max_order = (P.basis == RIDG_BASIS_Q && P.d == 1) ? kMaxOrderQ1 : kMaxOrder;
+  if (P.M > max_order) {
+    *msg = P.basis == RIDG_BASIS_Q && P.d == 1 ? "order above 12 is not implemented for the 1D tensor basis"
+                                               : "order above 5 is not implemented";
     return RIDG_E_UNSUPPORTED;
   }
   if (p->reserved != 0) {
@@ -379,6 +379,12 @@ int resolve_problem(const ridg_problem* p, Problem* out, std::string* msg) {
       !(solver == RIDG_SOLVER_PREFACTORED && brick_supported(P.d, P.M, P.n, true))) {
     *msg = "RIDG_FP32_REFINE is implemented for RIDG_SOLVER_REGION, and for RIDG_SOLVER_PREFACTORED in 3D at "
            "orders 2-3 on meshes with n[0] % 16 == 0, n[1] % 4 == 0, n[2] % 4 == 0";
+    return RIDG_E_UNSUPPORTED;
+  }
+  if (P.basis == RIDG_BASIS_Q &&
+      (P.d > 2 || P.flux != RIDG_FLUX_CONST || solver != RIDG_SOLVER_PREFACTORED || P.precision != RIDG_FP64)) {
+    *msg = "the tensor (Q) basis is implemented for constant-velocity FP64 problems in 1D and 2D (RIDG_SOLVER_AUTO or "
+           "RIDG_SOLVER_PREFACTORED, composite stencil)";
     return RIDG_E_UNSUPPORTED;
   }
   P.solver = solver;

@@ -126,8 +126,9 @@ extern "C" int ridg_advance_static(const ridg_problem* problem, const double* q_
   std::string msg;
   int rc = resolve_problem(problem, &P, &msg);
   if (rc) return static_fail(rc, msg);
-  if (P.flux != RIDG_FLUX_CONST || P.solver != RIDG_SOLVER_PREFACTORED || P.precision != RIDG_FP64)
-    return static_fail(RIDG_E_UNSUPPORTED, "ridg_advance_static runs constant-velocity FP64 problems (PREFACTORED)");
+  if (P.flux != RIDG_FLUX_CONST || P.solver != RIDG_SOLVER_PREFACTORED || P.precision != RIDG_FP64 ||
+      P.basis != RIDG_BASIS_P)
+    return static_fail(RIDG_E_UNSUPPORTED, "ridg_advance_static runs constant-velocity FP64 problems (PREFACTORED, total-degree basis)");
   if (!q_in || !q_out) return static_fail(RIDG_E_INVAL, "NULL state pointer");
   const int ns = n_space(P.d, P.M), nt = n_spacetime(P.d, P.M);
   if (count != (size_t)P.nel * ns) return static_fail(RIDG_E_INVAL, "count must equal n_elements * theta");

@@ -141,4 +141,28 @@ int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in
   return dispatch_dm<TapL>(d, M, kind, g, in, base, out, A, taps, ntaps, stream);
 }
 
+template <int D, int NS>
+static int composite_ns(const DevGeom& g, const double* in, double* out, const double* A, const int32_t* taps,
+                        int ntaps, void* stream) {
+  if (ntaps > kMaxTapUpdate) return (int)hipErrorInvalidValue;
+  TapsN tp;
+  for (int t = 0; t < kMaxTapUpdate; ++t)
+    for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  hipLaunchKernelGGL((tap_update_kernel<D, NS, NS>), dim3(grid_for(nel, 256)), dim3(256), 0, (hipStream_t)stream, g,
+                     in, in, out, A, tp, ntaps);
+  return (int)hipGetLastError();
+}
+
+int launch_tap_composite_ns(int d, int ns, const DevGeom& g, const double* in, double* out, const double* A,
+                            const int32_t* taps, int ntaps, void* stream) {
+#define RIDG_TC(DD, NN) \
+  if (d == DD && ns == NN) return composite_ns<DD, NN>(g, in, out, A, taps, ntaps, stream);
+  RIDG_TC(1, 1) RIDG_TC(1, 2) RIDG_TC(1, 3) RIDG_TC(1, 4) RIDG_TC(1, 5) RIDG_TC(1, 6) RIDG_TC(1, 7) RIDG_TC(1, 8)
+  RIDG_TC(1, 9) RIDG_TC(1, 10) RIDG_TC(1, 11) RIDG_TC(1, 12)
+  RIDG_TC(2, 1) RIDG_TC(2, 4) RIDG_TC(2, 9) RIDG_TC(2, 16) RIDG_TC(2, 25)
+#undef RIDG_TC
+  return (int)hipErrorInvalidValue;
+}
+
 }  // namespace ridg

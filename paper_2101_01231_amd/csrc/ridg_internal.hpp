@@ -12,17 +12,18 @@ namespace ridg {
 
 constexpr int kMaxDim = 3;
 constexpr int kMaxOrder = 5;
+constexpr int kMaxOrderQ1 = 12;  // tensor basis in 1D (composite stencil only)
 constexpr int kMaxBlocks = 27;  // 3^3 region elements
 constexpr uint8_t kOwn = 0xFF;  // plan face source: own trace (region boundary or outflow face)
 
 // ---------------------------------------------------------------- basis
 struct Basis {
-  int d = 0, M = 0;
+  int d = 0, M = 0, family = RIDG_BASIS_P;
   int theta = 0, theta_t = 0;
   std::vector<std::array<int, 4>> sidx;  // spatial exponents (a_1..a_d)
   std::vector<std::array<int, 4>> tidx;  // space-time exponents (b_t, b_1..b_d)
 };
-Basis make_basis(int d, int M);
+Basis make_basis(int d, int M, int family = RIDG_BASIS_P);
 
 // Exact 1D integrals of psi_m = sqrt(2m+1) P_m on [-1, 1].
 double leg_t3(int a, int b, int c);  // int psi_a psi_b psi_c
@@ -71,6 +72,7 @@ struct Problem {
   int refine = 0;
   int solver = 0;  // resolved
   int newton_max = 0;  // RIDG_FLUX_BURGERS: Newton iterations per region at most
+  int basis = RIDG_BASIS_P;
   int64_t nel = 0;
 };
 
@@ -265,6 +267,9 @@ int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, 
 // kind 0: correction taps (W -> Q' = Q + ...), kind 1: composite taps (Q -> Q' = Q + ...)
 int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                       const double* A, const int32_t* taps, int ntaps, void* stream);
+// The composite stencil for ns spatial modes (the tensor basis: ns = M in 1D up to 12, M^2 in 2D up to 25).
+int launch_tap_composite_ns(int d, int ns, const DevGeom& g, const double* in, double* out, const double* A,
+                            const int32_t* taps, int ntaps, void* stream);
 // The same tap operators on FP64 MFMA; frag = mfma_fragments(...) of the operator (device copy).
 constexpr int kMfmaPredict = 0, kMfmaCorrect = 1, kMfmaComposite = 2;
 constexpr size_t kMfmaMaxLds = 160 * 1024;  // fragments up to this size are staged in LDS

@@ -201,10 +201,18 @@ def workspace_bytes(problem):
     return out.value
 
 
+def _sizes(problem):
+    """(theta, theta_T) of the problem's basis family."""
+    from math import comb
+    d, M = problem.dim, problem.order
+    if problem.basis == BASIS_Q:
+        return M ** d, M ** (d + 1)
+    return comb(M - 1 + d, d), comb(M + d, d + 1)
+
+
 def host_region_matrix(problem, element, dt):
     d = problem.dim
-    from math import comb
-    nt = comb(problem.order + d, d + 1)
+    nt = _sizes(problem)[1]
     n = 3 ** d * nt
     A = np.empty((n, n))
     _check(lib().ridg_host_region_matrix(ctypes.byref(problem), element, dt, A.ctypes.data, A.size))
@@ -213,9 +221,7 @@ def host_region_matrix(problem, element, dt):
 
 def host_prediction_operator(problem, dt):
     d = problem.dim
-    from math import comb
-    nt = comb(problem.order + d, d + 1)
-    ns = comb(problem.order - 1 + d, d)
+    ns, nt = _sizes(problem)
     G = np.empty((nt, 3 ** d * ns))
     _check(lib().ridg_host_prediction_operator(ctypes.byref(problem), dt, G.ctypes.data, G.size))
     return G

@@ -89,7 +89,12 @@ BAD = [
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), refine_steps=9), ridg.RIDG_E_INVAL),
     (dict(dim=1, n=((1 << 20) + 1,), order=2, velocity=(1,)), ridg.RIDG_E_INVAL),  # axis above 2^20
     (dict(dim=3, n=(2048, 2048, 1024), order=1, velocity=(1, 1, 1)), ridg.RIDG_E_INVAL),  # 2^32 elements
-    (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), basis=ridg.BASIS_Q), ridg.RIDG_E_UNSUPPORTED),
+    (dict(dim=3, n=(8, 8, 8), order=2, velocity=(1, 1, 1), basis=ridg.BASIS_Q), ridg.RIDG_E_UNSUPPORTED),
+    (dict(dim=2, n=(8, 8), order=2, flux=ridg.FLUX_ROTATION, basis=ridg.BASIS_Q), ridg.RIDG_E_UNSUPPORTED),
+    (dict(dim=2, n=(8, 8), order=6, velocity=(1, 1), basis=ridg.BASIS_Q), ridg.RIDG_E_UNSUPPORTED),
+    (dict(dim=1, n=(8,), order=13, velocity=(1,), basis=ridg.BASIS_Q), ridg.RIDG_E_UNSUPPORTED),
+    (dict(dim=1, n=(8,), order=3, velocity=(1,), basis=ridg.BASIS_Q, solver=ridg.SOLVER_REGION),
+     ridg.RIDG_E_UNSUPPORTED),
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), basis=7), ridg.RIDG_E_INVAL),
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), length=(1.0, -2.0)), ridg.RIDG_E_INVAL),
     (dict(dim=2, n=(8, 8), order=2, velocity=(1, 1), length=(float("inf"), 1.0)), ridg.RIDG_E_INVAL),
@@ -220,3 +225,45 @@ def test_burgers_problems_validated():
     p = ridg.make_problem(2, (4, 4), 3, flux=ridg.FLUX_BURGERS)
     with pytest.raises(ridg.RidgError):
         ridg.host_region_matrix(p, 0, 0.01)
+
+
+Q_CASES = [
+    dict(dim=1, n=(7,), order=4, velocity=(1.0,), basis=ridg.BASIS_Q),
+    dict(dim=1, n=(5,), order=12, velocity=(-0.7,), basis=ridg.BASIS_Q),
+    dict(dim=2, n=(5, 4), order=3, velocity=(0.9, -0.4), basis=ridg.BASIS_Q),
+]
+
+
+@pytest.mark.parametrize("case", Q_CASES)
+def test_tensor_basis_operators_match_oracle(case):
+    """The tensor (Q) space of Sec. 2.1-2.2: the library's QQF region matrix and prediction operator
+    against the oracle's quadrature with family 'Q'."""
+    p = ridg.make_problem(**case)
+    d = p.dim
+    prob = S.Problem(d=d, n=tuple(p.n[i] for i in range(d)), M=p.order,
+                     velocity=("const", tuple(p.velocity[i] for i in range(d))), family="Q")
+    assert prob.theta == p.order ** d and prob.theta_t == p.order ** (d + 1)
+    dt = 0.5 / max(prob.n)
+    A = ridg.host_region_matrix(p, 0, dt)
+    Ao, _, c, _ = S.region_system(prob, 0, np.zeros((prob.n_el, prob.theta)), dt)
+    np.testing.assert_allclose(A, Ao, atol=1e-12 * max(1.0, np.abs(Ao).max()))
+    G = ridg.host_prediction_operator(p, dt)
+    nb = 3 ** d
+    B = scipy.linalg.block_diag(*[S.element_blocks(prob, 0, dt)["C"]] * nb)
+    Go = np.linalg.solve(Ao, B)[c * prob.theta_t:(c + 1) * prob.theta_t]
+    np.testing.assert_allclose(G, Go, atol=1e-12 * max(1.0, np.abs(Go).max()))
+
+
+def test_tensor_basis_spectral_radius_matches_oracle():
+    """von Neumann amplification of the 1D tensor-basis step at the paper's CFL 0.9 (Sec. 6.1): the library
+    and the oracle's independent analysis (impulse responses of its own step) agree; at 0.9 the step is
+    neutral to within 2e-5 per step (1 + 1.4e-5 at order 4, 1 + 9e-7 at order 6), and stable to
+    rounding at 0.7."""
+    from oracle import stability as ST
+    for M in (4, 6):
+        p = ridg.make_problem(1, (16,), M, velocity=(1.0,), basis=ridg.BASIS_Q)
+        rho = ridg.host_spectral_radius(p, 0.9 / 16, nk=64)
+        ref = ST.spectral_radius(ST.stencil(1, M, (1.0,), 0.9, "Q"), 1, 64)
+        assert abs(rho - ref) <= 1e-12
+        assert 1.0 - 1e-12 <= rho <= 1.0 + 2e-5
+        assert ridg.host_spectral_radius(p, 0.7 / 16, nk=64) <= 1.0 + 1e-12
