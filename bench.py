@@ -46,7 +46,8 @@ KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
                 "predict_tear_kernel": ["k_tear_dense.hip"], "predict_dense_kernel": ["k_tear_dense.hip"],
                 "batch_predict_kernel": ["k_batch.hip"], "batch_correct_kernel": ["k_batch.hip"],
                 "tap_mfma_kernel": ["k_mfma.hip"], "brick_step_kernel": ["k_brick.hip"],
-                "burgers_predict_kernel": ["k_burgers.hip"], "burgers_correct_kernel": ["k_burgers.hip"]}
+                "burgers_predict_kernel": ["k_burgers.hip"], "burgers_correct_kernel": ["k_burgers.hip"],
+                "tap_zmarch_kernel": ["k_stencil3d.hip"]}
 RECORD_TAG = "traffic-record: "
 
 
@@ -76,6 +77,8 @@ def dominant_kernel(info, opts, precision):
             cols = info.theta
             rows = info.theta if opts.get("composite") else info.theta_t
             return f"ridg::tap_mfma_kernel<{rows}, {cols}>"
+        if opts.get("composite") == 2:
+            return f"ridg::tap_zmarch_kernel<{info.theta}>"
         if opts.get("composite"):
             return f"ridg::tap_update_kernel<{d}, {info.theta}, {info.theta}>"
         return f"ridg::predict_prefactored_kernel<{d}, {M}>"
@@ -526,7 +529,8 @@ def main():
         nflops = (info.flops_predict + info.flops_correct) if brick else (info.flops_composite if comp else info.flops_predict)
         bw = nbytes / (R["pred_ms"] * 1e-3) / 1e9
         tf = nflops / (R["pred_ms"] * 1e-3) / 1e12
-        kern = "composite prediction+correction stencil" if comp else "prediction (prefactored G)"
+        kern = ("composite prediction+correction stencil" + (" marched along z through LDS" if comp == 2 else "")
+                if comp else "prediction (prefactored G)")
         mfma = bool(R["opts"].get("mfma"))
         if brick:
             kern = ("fused brick step (FP32 matrix-core predictions, FP64 correction)" if best == "fp32" else

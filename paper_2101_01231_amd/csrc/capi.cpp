@@ -901,6 +901,10 @@ static int direct_step(ridg_t* h, double dt) {
     int err = launch_tap_composite_ns(P.d, h->T.ns, h->geom, h->Q[h->cur], h->Q[1 - h->cur], h->Kc,
                                       h->host_ktaps.data(), nk, h->stream);
     if (err) return hip_fail(err, "composite launch");
+  } else if (pref && h->opt_composite == 2) {  // the same stencil marched along z through LDS
+    int err = launch_tap_zmarch(h->T.ns, h->geom, h->Q[h->cur], h->Q[1 - h->cur], h->Kc, h->host_ktaps.data(), nk,
+                                h->stream);
+    if (err) return hip_fail(err, "z-marched composite launch");
   } else if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
     int err = mfma ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
                                             h->Q[1 - h->cur], h->Fk, h->host_ktaps.data(), nk, h->stream)
@@ -1128,7 +1132,7 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
 
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
-  const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : 1;
+  const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : (option == RIDG_OPT_COMPOSITE ? 2 : 1);
   if (value < 0 || value > vmax) return fail(RIDG_E_INVAL, "option value out of range");
   if (h->P.solver == RIDG_SOLVER_NEWTON && value)
     return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no execution options");
@@ -1154,6 +1158,9 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
     case RIDG_OPT_COMPOSITE:
       if (value && h->P.solver != RIDG_SOLVER_PREFACTORED)
         return fail(RIDG_E_UNSUPPORTED, "the composite stencil needs the PREFACTORED solver");
+      if (value == 2 && !zmarch_supported(h->P.d, h->T.ns, h->P.n[0], h->P.n[1], h->P.n[2]))
+        return fail(RIDG_E_UNSUPPORTED, "the z-marched composite stencil needs 3D, order 2-3, n[0] and n[1] multiples "
+                                        "of 16 and n[2] a multiple of 8 (or at most 64)");
       h->opt_composite = (int)value;
       break;
     case RIDG_OPT_MFMA:
@@ -1234,6 +1241,7 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
     for (int l : layouts)
       for (int c = 0; c < (pref ? 2 : 1); ++c)
         for (int m = 0; m < (pref ? 2 : 1); ++m) cands.push_back({g, l, 0, c, m, 0});
+    if (pref && zmarch_supported(h->P.d, h->T.ns, h->P.n[0], h->P.n[1], h->P.n[2])) cands.push_back({g, 0, 0, 2, 0, 0});
     if (h->brick_ok) cands.push_back({g, 0, 0, 0, 0, 1});
   }
   if (fusable && !f32_brick) cands.push_back({0, 0, 1, 0, 0, 0});

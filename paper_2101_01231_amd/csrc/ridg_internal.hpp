@@ -267,6 +267,15 @@ int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, 
 // kind 0: correction taps (W -> Q' = Q + ...), kind 1: composite taps (Q -> Q' = Q + ...)
 int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                       const double* A, const int32_t* taps, int ntaps, void* stream);
+// The composite stencil in 3D marched along z with a ring of three state planes in LDS (k_stencil3d.hip):
+// theta 4 or 10 (orders 2-3), n0 and n1 multiples of 16, n2 a multiple of 8 or at most 64.
+struct ZMarch {
+  int8_t lo[3], hi[3];  // tap offset range per axis (span <= 2)
+  int32_t tz;           // planes per workgroup
+};
+bool zmarch_supported(int d, int ns, int n0, int n1, int n2);
+int launch_tap_zmarch(int ns, const DevGeom& g, const double* in, double* out, const double* A, const int32_t* taps,
+                      int ntaps, void* stream);
 // The composite stencil for ns spatial modes (the tensor basis: ns = M in 1D up to 12, M^2 in 2D up to 25).
 int launch_tap_composite_ns(int d, int ns, const DevGeom& g, const double* in, double* out, const double* A,
                             const int32_t* taps, int ntaps, void* stream);
