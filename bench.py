@@ -381,6 +381,10 @@ def serving(args):
                    "mem_budget_gb": args.mem_gb},
         "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"], "samples": st["latency_samples"]},
         "wall_s": st["wall_s"], "busy_s": st["busy_s"], "busy_fraction": st["busy_s"] / st["wall_s"],
+        # the arrival process leaves the system empty much of the time (20 requests/s of ~10 ms each):
+        # the server's own efficiency is the busy time over the time with requests in the system
+        "idle_s": st["idle_s"],
+        "busy_fraction_with_requests": st["busy_s"] / max(st["wall_s"] - st["idle_s"], 1e-9),
         "mean_active": st["mean_active"],
         "st_dof_updates_per_s_wall": st["st_dof_updates_per_s_wall"], "rejected": len(st["rejected"]),
     }

@@ -110,6 +110,7 @@ class Server:
         results, rejected = {}, {}
         lat_ms, tick_ms, active_counts = [], [], []
         st_updates = 0
+        idle = 0.0  # wall time with no request in the system (waiting for the next arrival)
         t0 = time.perf_counter()
 
         def account(tick):
@@ -178,14 +179,16 @@ class Server:
                 retire_ready(block=not (pending or waiting))
                 continue
             if pending and not waiting:
+                ts = time.perf_counter()
                 time.sleep(max(0.0, (pending[0].arrival - now) / time_scale))
+                idle += time.perf_counter() - ts
             elif waiting and not retiring:
                 # nothing active and the head of the queue does not fit: it never will
                 rejected[waiting.popleft().id] = "does not fit the memory budget"
         wall = time.perf_counter() - t0
         busy = sum(tick_ms) * 1e-3
         lat = np.array(lat_ms) if lat_ms else np.zeros(1)
-        return dict(results=results, rejected=rejected, wall_s=wall, busy_s=busy, ticks=len(tick_ms),
+        return dict(results=results, rejected=rejected, wall_s=wall, busy_s=busy, idle_s=idle, ticks=len(tick_ms),
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     latency_samples=int(lat.size),
                     mean_active=float(np.mean(active_counts)) if active_counts else 0.0,
