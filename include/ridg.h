@@ -227,10 +227,7 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
  *     step's dt (growth factor <= 64 on every diagonal block form); otherwise the step falls back
  *     to layout 4 (FP64) or 1 (RIDG_FP32_REFINE). Results agree with the other layouts to rounding.
  *   RIDG_OPT_FUSED (PREFACTORED, meshes whose state and predictions fit in 160 KB of LDS): run all
- *     n_steps of a ridg_step call in one single-workgroup kernel. 2 (PREFACTORED, FP64, any mesh): run
- *     all n_steps as the composite stencil in one cooperative launch of the workgroups resident at
- *     once, with a grid-wide barrier between steps (bitwise equal to RIDG_OPT_COMPOSITE steps). Not
- *     used while stage timing is on. */
+ *     n_steps of a ridg_step call in one single-workgroup kernel. */
 #define RIDG_OPT_GRAPH 1
 #define RIDG_OPT_PLAN_LAYOUT 2
 #define RIDG_OPT_FUSED 3

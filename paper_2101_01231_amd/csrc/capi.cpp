@@ -995,16 +995,7 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
   if (rc) return rc;
   const int warn = stability_warning(h, dt);
   if (warn < 0) return warn;
-  if (h->opt_fused == 2 && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && h->P.precision == RIDG_FP64 &&
-      h->P.basis == RIDG_BASIS_P) {
-    const int nk = (int)h->host_ktaps.size() / 3;
-    int err = launch_persistent_composite(h->P.d, h->P.M, h->geom, h->Q[h->cur], h->Q[1 - h->cur], h->Kc,
-                                          h->host_ktaps.data(), nk, n_steps, h->stream);
-    if (err) return hip_fail(err, "persistent launch");
-    h->cur ^= (n_steps & 1);
-    return warn;
-  }
-  if (h->opt_fused == 1 && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && h->P.precision == RIDG_FP64 &&
+  if (h->opt_fused && !h->timing && h->P.solver == RIDG_SOLVER_PREFACTORED && h->P.precision == RIDG_FP64 &&
       fused_fits(h->P.d, h->P.M, h->P.nel)) {
     int err = launch_fused_prefactored(h->P.d, h->P.M, h->geom, dt, h->Q[h->cur], h->Q[1 - h->cur], h->G,
                                        h->host_taps.data(), h->ntaps, h->dt, n_steps, h->stream);
@@ -1141,8 +1132,7 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
 
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
-  const int64_t vmax =
-      option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : ((option == RIDG_OPT_COMPOSITE || option == RIDG_OPT_FUSED) ? 2 : 1);
+  const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : (option == RIDG_OPT_COMPOSITE ? 2 : 1);
   if (value < 0 || value > vmax) return fail(RIDG_E_INVAL, "option value out of range");
   if (h->P.solver == RIDG_SOLVER_NEWTON && value)
     return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no execution options");
@@ -1161,10 +1151,8 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
       h->opt_layout = (int)value;
       break;
     case RIDG_OPT_FUSED:
-      if (value == 1 && (h->P.solver != RIDG_SOLVER_PREFACTORED || !fused_fits(h->P.d, h->P.M, h->P.nel)))
+      if (value && (h->P.solver != RIDG_SOLVER_PREFACTORED || !fused_fits(h->P.d, h->P.M, h->P.nel)))
         return fail(RIDG_E_UNSUPPORTED, "fused steps need the PREFACTORED solver and a mesh that fits in LDS");
-      if (value == 2 && (h->P.solver != RIDG_SOLVER_PREFACTORED || h->P.precision != RIDG_FP64))
-        return fail(RIDG_E_UNSUPPORTED, "persistent steps need the PREFACTORED solver in FP64");
       h->opt_fused = (int)value;
       break;
     case RIDG_OPT_COMPOSITE:
@@ -1257,7 +1245,6 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
     if (h->brick_ok) cands.push_back({g, 0, 0, 0, 0, 1});
   }
   if (fusable && !f32_brick) cands.push_back({0, 0, 1, 0, 0, 0});
-  if (pref && h->P.precision == RIDG_FP64) cands.push_back({0, 0, 2, 1, 0, 0});  // persistent composite steps
   // keep the state: tuning steps run on a copy that is restored afterwards
   const size_t bytes = (size_t)h->P.nel * h->T.ns * 8;
   const int cur0 = h->cur;

@@ -1,8 +1,6 @@
 // Constant-velocity prediction with the host-prefactored operator G (Sec. 2.2, one linear solve),
 // and the fused small-mesh kernel that runs whole RIDG steps (prediction, then correction, Sec.
 // 2.3) on one workgroup with the mesh state resident in LDS.
-#include <hip/hip_cooperative_groups.h>
-
 #include "kernels_common.hpp"
 
 namespace ridg {
@@ -141,65 +139,6 @@ struct TapL {
 int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                       const double* A, const int32_t* taps, int ntaps, void* stream) {
   return dispatch_dm<TapL>(d, M, kind, g, in, base, out, A, taps, ntaps, stream);
-}
-
-// ---------------------------------------------------------------- persistent multi-step composite
-// All n_steps of a ridg_step call in one cooperative launch of as many workgroups as are resident at
-// once: each step applies the composite taps (Q' = Q + sum_o K_o Q_{e+o}) over a grid-stride range
-// of elements from one state buffer into the other, and a grid-wide barrier (cooperative groups)
-// separates the steps. The grid size is checked against residency by the cooperative launch itself.
-// Measured on the 2D 256^2 order-3 stencil: 36.8 us per step against 6.6 us for one launch per step
-// (the barrier, with the cache maintenance that makes one step's stores visible on every XCD, costs
-// more than a launch, with 256 or with 2048 workgroups alike), so the autotuner keeps launches there.
-template <int D, int NS>
-__global__ __launch_bounds__(256) void persistent_composite_kernel(DevGeom g, double* __restrict__ QA,
-                                                                   double* __restrict__ QB,
-                                                                   const double* __restrict__ K, TapsN taps,
-                                                                   int ntaps, int n_steps) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
-  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int s = 0; s < n_steps; ++s) {
-    const double* src = (s & 1) ? QB : QA;
-    double* dst = (s & 1) ? QA : QB;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nel; e += stride)
-      tap_update_elem<NS, NS>(g, src, src, dst, K, taps, ntaps, e, nel);
-    if (s + 1 < n_steps) grid.sync();
-  }
-}
-
-template <int D, int M>
-struct PersistentL {
-  static int run(const DevGeom& g, double* QA, double* QB, const double* K, const int32_t* taps, int ntaps,
-                 int n_steps, void* stream) {
-    constexpr int NS = n_space(D, M);
-    if (ntaps > kMaxTapUpdate || n_steps < 1) return (int)hipErrorInvalidValue;
-    TapsN tp;
-    for (int t = 0; t < kMaxTapUpdate; ++t)
-      for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
-    static int resident = [] {
-      int dev = 0, cus = 0, per = 0;
-      if (hipGetDevice(&dev) || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) ||
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)persistent_composite_kernel<D, NS>, 256, 0))
-        return 0;
-      return cus * per;
-    }();
-    if (resident <= 0) return (int)hipErrorInvalidValue;
-    const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
-    const int64_t want = (nel + 255) / 256;
-    const unsigned grid = (unsigned)(want < resident ? want : resident);
-    DevGeom gg = g;
-    int ns = n_steps, nt = ntaps;
-    void* args[] = {&gg, &QA, &QB, (void*)&K, &tp, &nt, &ns};
-    return (int)hipLaunchCooperativeKernel((const void*)persistent_composite_kernel<D, NS>, dim3(grid), dim3(256),
-                                           args, 0, (hipStream_t)stream);
-  }
-};
-
-int launch_persistent_composite(int d, int M, const DevGeom& g, double* QA, double* QB, const double* K,
-                                const int32_t* taps, int ntaps, int n_steps, void* stream) {
-  return dispatch_dm<PersistentL>(d, M, g, QA, QB, K, taps, ntaps, n_steps, stream);
 }
 
 template <int D, int NS>

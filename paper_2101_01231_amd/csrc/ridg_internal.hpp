@@ -267,10 +267,6 @@ int launch_predict_prefactored(int d, int M, const DevGeom& g, const double* Q, 
 // kind 0: correction taps (W -> Q' = Q + ...), kind 1: composite taps (Q -> Q' = Q + ...)
 int launch_tap_update(int d, int M, int kind, const DevGeom& g, const double* in, const double* base, double* out,
                       const double* A, const int32_t* taps, int ntaps, void* stream);
-// All n_steps of the composite stencil in one cooperative launch (grid-wide barrier between steps);
-// the state alternates between QA and QB starting from QA (after n steps it is in QB when n is odd).
-int launch_persistent_composite(int d, int M, const DevGeom& g, double* QA, double* QB, const double* K,
-                                const int32_t* taps, int ntaps, int n_steps, void* stream);
 // The composite stencil in 3D marched along z with a ring of three state planes in LDS (k_stencil3d.hip):
 // theta 4 or 10 (orders 2-3), n0 and n1 multiples of 16, n2 a multiple of 8 or at most 64.
 struct ZMarch {
