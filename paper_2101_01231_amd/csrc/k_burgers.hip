@@ -11,7 +11,8 @@
 //      Jacobian2), face terms (Rusanov inside the region, own-trace physical flux on its boundary)
 //      and their Jacobian blocks by face quadrature,
 //   4. solves J delta = R by Gaussian elimination with partial pivoting in LDS (FP64 for the systems of
-//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2) and updates W <- W - delta,
+//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2; one row per thread above 128 unknowns,
+//      the update's 4-entry chunks spread over the workgroup below) and updates W <- W - delta,
 //      until max|delta| <= 1e-13 max(1, max|W|) or the iteration limit.
 // Only the centre's W is written. The Rusanov wave speed of a face is max(|mean q_a|, |mean q_b|)
 // from the two elements' states at t^n (fixed during the iteration).
@@ -31,9 +32,22 @@ constexpr int kBurgersThreads = 256;
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
+// The elimination keeps one row per thread for systems above this size (newton_solve_rows) and
+// spreads the 4-entry chunks of the rank-1 update over the workgroup below it (newton_solve):
+// measured per Burgers step at 128^2, N = 180: 90.5 against 98.3 ms; N = 90: 10.9 against 10.5 ms;
+// N = 36: 3.0 against 2.6 ms.
+constexpr int kRowsSolveMin = 128;
+
+// Row stride of the augmented matrix in LDS: a multiple of 4 entries (the updates move 4-entry
+// chunks); for the one-row-per-thread elimination also an odd number of chunks, so that the 16-byte
+// chunks of consecutive rows fall in distinct banks.
+__host__ __device__ constexpr int burgers_ldp(int n) {
+  return (n > kRowsSolveMin && (((n + 4) & ~3) / 4) % 2 == 0) ? ((n + 4) & ~3) + 4 : ((n + 4) & ~3);
+}
+
 template <int D, int M>
 struct BCfg {
-  static constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NB = pow3(D), N = NB * NT, LD = N + 1;
+  static constexpr int NS = n_space(D, M), NT = n_spacetime(D, M), NB = pow3(D), N = NB * NT;
   static constexpr int Q = burgers_q(M), NQ = ipow(Q, D + 1), NQF = ipow(Q, D), NF = 2 * D;
 };
 
@@ -83,9 +97,9 @@ __device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, doubl
                                         const double* s_W, const double* s_q, const double* s_wv,
                                         const double* s_wf, const double* s_fp, TS* __restrict__ row) {
   using C = BCfg<D, M>;
-  constexpr int NS = C::NS, NT = C::NT, N = C::N, LD = C::LD, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  constexpr int NS = C::NS, NT = C::NT, N = C::N, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
   const int r = R / NT, k = R % NT;
-  for (int j = 0; j < ((LD + 3) & ~3); ++j) row[j] = (TS)0;
+  for (int j = 0; j < burgers_ldp(N); ++j) row[j] = (TS)0;
   double dg[NT];
   double res = 0.0;
 #pragma unroll
@@ -172,7 +186,7 @@ __device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, doubl
 // entries left of c are dead (the factor L is not kept) and may take any value.
 template <int N, class TS>
 __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv, int* s_key) {
-  constexpr int LD = N + 1, LDP = (LD + 3) & ~3, NW = kBurgersThreads / 64;
+  constexpr int LDP = burgers_ldp(N), NW = kBurgersThreads / 64;
   constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : 10);
   constexpr unsigned RMASK = (1u << RB) - 1u;
   typedef TS v4 __attribute__((ext_vector_type(4)));
@@ -228,6 +242,73 @@ __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv
   }
 }
 
+// Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A in LDS, one row
+// per thread and no row exchanges: row p_c, the unused row of largest |A[r][c]| (the same 32-bit
+// key as newton_solve), pivots column c, and every unused row r subtracts (A[r][c] / A[p_c][c]) times
+// it from the 4-aligned column at or below c on (entries left of c are dead). Each thread forms its
+// row's key for the next column right after its update, so a column costs one workgroup barrier.
+// Back substitution runs over the pivot rows, x_c = (b_{p_c} - sum_{j>c} A[p_c][j] x_j) / A[p_c][c],
+// one barrier per column; the solution goes to s_x in FP64.
+template <int N, class TS>
+__device__ __noinline__ void newton_solve_rows(TS* A, double* s_x, TS* s_pv, int* s_perm, int* s_key) {
+  constexpr int LDP = burgers_ldp(N), NW = kBurgersThreads / 64;
+  static_assert(N <= kBurgersThreads, "one row per thread");
+  constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : 10);
+  constexpr unsigned RMASK = (1u << RB) - 1u;
+  typedef TS v4 __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const bool has_row = tid < N;
+  bool used = !has_row;
+  int mycol = N;  // the column this row pivots
+  TS* Ar = A + (has_row ? tid : 0) * LDP;
+  auto publish_key = [&](int c) {
+    unsigned k = 0u;
+    if (!used) k = (__float_as_uint((float)fabs((double)Ar[c])) & ~RMASK) | (RMASK - (unsigned)tid);
+    k = seg_max_pow2<64>(k);
+    if (lane == 0) s_key[(c & 1) * NW + wid] = (int)k;
+  };
+  publish_key(0);
+  __syncthreads();
+  for (int c = 0; c < N; ++c) {
+    unsigned best = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) best = max(best, (unsigned)s_key[(c & 1) * NW + w]);
+    const int p = (int)(RMASK - (best & RMASK));
+    const TS* Ap = A + p * LDP;
+    const TS pvc = Ap[c];
+    if (tid == 0) {
+      s_perm[c] = p;
+      s_pv[c] = pvc;
+    }
+    if (tid == p) {
+      used = true;
+      mycol = c;
+    }
+    if (!used) {
+      const TS l = Ar[c] * ((TS)1 / pvc);
+#pragma unroll 4
+      for (int j = c & ~3; j < LDP; j += 4) {
+        v4* a = (v4*)(Ar + j);
+        const v4 pv = *(const v4*)(Ap + j);
+        v4 x = *a;
+        x.x = fma(-l, pv.x, x.x);
+        x.y = fma(-l, pv.y, x.y);
+        x.z = fma(-l, pv.z, x.z);
+        x.w = fma(-l, pv.w, x.w);
+        *a = x;
+      }
+    }
+    if (c + 1 < N) publish_key(c + 1);
+    __syncthreads();
+  }
+  for (int c = N - 1; c >= 0; --c) {
+    const double xc = (double)A[s_perm[c] * LDP + N] / (double)s_pv[c];
+    if (tid == 0) s_x[c] = xc;
+    if (mycol < c) Ar[N] = fma(-Ar[c], (TS)xc, Ar[N]);
+    __syncthreads();
+  }
+}
+
 // Arithmetic of the region Jacobian's elimination: FP64 for the small systems (up to 48 KB), FP32
 // otherwise, which halves the LDS of a workgroup and so raises the workgroups resident per CU (the
 // residual stays FP64, so Newton converges to the same FP64 root; an FP32 step only makes the
@@ -243,11 +324,11 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
                                                                           int64_t first, int64_t nel, int max_iter,
                                                                           int32_t* __restrict__ stats) {
   using C = BCfg<D, M>;
-  constexpr int NS = C::NS, NT = C::NT, NB = C::NB, N = C::N, LD = C::LD, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  constexpr int NS = C::NS, NT = C::NT, NB = C::NB, N = C::N, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
   const int64_t e = first + blockIdx.x;
   if (e >= nel) return;
   using TS = NewtonScalar<N>;
-  constexpr int LDP = (LD + 3) & ~3;
+  constexpr int LDP = burgers_ldp(N);
   __shared__ __align__(16) TS s_A[N * LDP];  // [N][LDP]: Jacobian | residual | padding
   __shared__ double s_W[N];
   __shared__ double s_q[NB * NS];
@@ -257,7 +338,8 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
   __shared__ double s_x[N];
   __shared__ __align__(16) TS s_piv[LDP];
   __shared__ TS s_l[N];
-  __shared__ int s_key[kBurgersThreads / 64];
+  __shared__ int s_key[2 * (kBurgersThreads / 64)];
+  __shared__ int s_perm[N];
   __shared__ double s_red[2][kBurgersThreads / 64];
   __shared__ int64_t s_ge[NB];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -293,7 +375,10 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
     for (int R = tid; R < N; R += kBurgersThreads)
       newton_row<D, M, TS>(t, c0, c1, c2, R, s_W, s_q, s_wv, s_wf, s_fp, s_A + R * LDP);
     __syncthreads();
-    newton_solve<N, TS>(s_A, s_x, s_l, s_piv, s_key);
+    if constexpr (N > kRowsSolveMin)
+      newton_solve_rows<N, TS>(s_A, s_x, s_l, s_perm, s_key);
+    else
+      newton_solve<N, TS>(s_A, s_x, s_l, s_piv, s_key);
     // update and convergence test (uniform across the workgroup)
     double md = 0.0, mw = 0.0;
     for (int x = tid; x < N; x += kBurgersThreads) {
