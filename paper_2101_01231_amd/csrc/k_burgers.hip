@@ -11,7 +11,7 @@
 //      Jacobian2), face terms (Rusanov inside the region, own-trace physical flux on its boundary)
 //      and their Jacobian blocks by face quadrature,
 //   4. solves J delta = R by Gaussian elimination with partial pivoting in LDS (FP64 for the systems of
-//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2; one row per thread above 128 unknowns,
+//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2; two threads per row above 128 unknowns,
 //      the update's 4-entry chunks spread over the workgroup below) and updates W <- W - delta,
 //      until max|delta| <= 1e-13 max(1, max|W|) or the iteration limit.
 // Only the centre's W is written. The Rusanov wave speed of a face is max(|mean q_a|, |mean q_b|)
@@ -28,15 +28,20 @@ namespace ridg {
 namespace {
 
 constexpr double kNewtonTol = 1e-13;
-constexpr int kBurgersThreads = 256;
+
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-// The elimination keeps one row per thread for systems above this size (newton_solve_rows) and
-// spreads the 4-entry chunks of the rank-1 update over the workgroup below it (newton_solve):
-// measured per Burgers step at 128^2, N = 180: 90.5 against 98.3 ms; N = 90: 10.9 against 10.5 ms;
-// N = 36: 3.0 against 2.6 ms.
+// The elimination keeps each row with its own threads for systems above this size
+// (newton_solve_rows) and spreads the 4-entry chunks of the rank-1 update over the workgroup below
+// it (newton_solve).
 constexpr int kRowsSolveMin = 128;
+
+// Threads of a region's workgroup: 512 where the region system's LDS leaves room for one workgroup
+// per CU (two wavefronts per SIMD, two threads per row in the elimination), 256 otherwise (several
+// workgroups per CU). Measured per Burgers step at 128^2 with two threads per row against one:
+// order 4 (N = 180), 79.4 against 89.5 ms; at 512 threads, order 3 (N = 90) took 18.3 against 10.5 ms.
+__host__ __device__ constexpr int burgers_threads(int n) { return n > kRowsSolveMin ? 512 : 256; }
 
 // Row stride of the augmented matrix in LDS: a multiple of 4 entries (the updates move 4-entry
 // chunks); for the one-row-per-thread elimination also an odd number of chunks, so that the 16-byte
@@ -65,22 +70,22 @@ template <int D, int M>
 __device__ __noinline__ void newton_points(const BurgersDev& t, const double* s_W, double* s_wv, double* s_wf,
                                            double* s_fp) {
   using C = BCfg<D, M>;
-  constexpr int NT = C::NT, NB = C::NB, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
+  constexpr int NT = C::NT, NB = C::NB, NQ = C::NQ, NQF = C::NQF, NF = C::NF, TH = burgers_threads(C::N);
   const int tid = threadIdx.x;
-  for (int x = tid; x < NB * NQ; x += kBurgersThreads) {
+  for (int x = tid; x < NB * NQ; x += TH) {
     const int r = x / NQ, pt = x % NQ;
     double v = 0.0;
     for (int l = 0; l < NT; ++l) v = fma(t.psiv[l * NQ + pt], s_W[r * NT + l], v);
     s_wv[x] = v;
   }
-  for (int x = tid; x < NB * NF * NQF; x += kBurgersThreads) {
+  for (int x = tid; x < NB * NF * NQF; x += TH) {
     const int r = x / (NF * NQF), f = (x / NQF) % NF, pf = x % NQF;
     double v = 0.0;
     for (int l = 0; l < NT; ++l) v = fma(t.psif[(f * NT + l) * NQF + pf], s_W[r * NT + l], v);
     s_wf[x] = v;
   }
   __syncthreads();
-  for (int x = tid; x < NB * NT; x += kBurgersThreads) {
+  for (int x = tid; x < NB * NT; x += TH) {
     const int r = x / NT, p = x % NT;
     double v = 0.0;
     for (int pt = 0; pt < NQ; ++pt) v = fma(t.projw[p * NQ + pt], s_wv[r * NQ + pt], v);
@@ -186,14 +191,14 @@ __device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, doubl
 // entries left of c are dead (the factor L is not kept) and may take any value.
 template <int N, class TS>
 __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv, int* s_key) {
-  constexpr int LDP = burgers_ldp(N), NW = kBurgersThreads / 64;
+  constexpr int LDP = burgers_ldp(N), TH = burgers_threads(N), NW = TH / 64;
   constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : 10);
   constexpr unsigned RMASK = (1u << RB) - 1u;
   typedef TS v4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int c = 0; c < N; ++c) {
     unsigned key = 0u;
-    for (int Rr = c + tid; Rr < N; Rr += kBurgersThreads) {
+    for (int Rr = c + tid; Rr < N; Rr += TH) {
       const unsigned kk = (__float_as_uint((float)fabs((double)A[Rr * LDP + c])) & ~RMASK) | (RMASK - (unsigned)Rr);
       key = max(key, kk);
     }
@@ -204,7 +209,7 @@ __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv
     for (int w = 0; w < NW; ++w) best = max(best, (unsigned)s_key[w]);
     const int p = (int)(RMASK - (best & RMASK));
     const int j0 = c & ~3;
-    for (int j = j0 + tid; j < LDP; j += kBurgersThreads) {
+    for (int j = j0 + tid; j < LDP; j += TH) {
       const TS vc = A[c * LDP + j], vp = A[p * LDP + j];
       if (p != c && j >= c) {
         A[c * LDP + j] = vp;
@@ -214,11 +219,11 @@ __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv
     }
     __syncthreads();
     const TS inv = (TS)1 / s_piv[c];
-    for (int Rr = c + 1 + tid; Rr < N; Rr += kBurgersThreads) s_l[Rr] = A[Rr * LDP + c] * inv;
+    for (int Rr = c + 1 + tid; Rr < N; Rr += TH) s_l[Rr] = A[Rr * LDP + c] * inv;
     __syncthreads();
     const int nch = (LDP - j0) >> 2, items = (N - c - 1) * nch;
 #pragma unroll 4
-    for (int q = tid; q < items; q += kBurgersThreads) {
+    for (int q = tid; q < items; q += TH) {
       const int rr = q / nch, ch = q - rr * nch;
       const int Rr = c + 1 + rr;
       v4* a = (v4*)(A + Rr * LDP + j0) + ch;
@@ -237,13 +242,13 @@ __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv
     if (tid == 0) s_x[c] = (double)A[c * LDP + N] / (double)A[c * LDP + c];
     __syncthreads();
     const TS xc = (TS)s_x[c];
-    for (int Rr = tid; Rr < c; Rr += kBurgersThreads) A[Rr * LDP + N] = fma(-A[Rr * LDP + c], xc, A[Rr * LDP + N]);
+    for (int Rr = tid; Rr < c; Rr += TH) A[Rr * LDP + N] = fma(-A[Rr * LDP + c], xc, A[Rr * LDP + N]);
     __syncthreads();
   }
 }
 
-// Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A in LDS, one row
-// per thread and no row exchanges: row p_c, the unused row of largest |A[r][c]| (the same 32-bit
+// Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A in LDS, two
+// threads per row and no row exchanges: row p_c, the unused row of largest |A[r][c]| (the same 32-bit
 // key as newton_solve), pivots column c, and every unused row r subtracts (A[r][c] / A[p_c][c]) times
 // it from the 4-aligned column at or below c on (entries left of c are dead). Each thread forms its
 // row's key for the next column right after its update, so a column costs one workgroup barrier.
@@ -251,23 +256,25 @@ __device__ __noinline__ void newton_solve(TS* A, double* s_x, TS* s_l, TS* s_piv
 // one barrier per column; the solution goes to s_x in FP64.
 template <int N, class TS>
 __device__ __noinline__ void newton_solve_rows(TS* A, double* s_x, TS* s_pv, int* s_perm, int* s_key) {
-  constexpr int LDP = burgers_ldp(N), NW = kBurgersThreads / 64;
-  static_assert(N <= kBurgersThreads, "one row per thread");
+  constexpr int LDP = burgers_ldp(N), TH = burgers_threads(N), NW = TH / 64;
+  static_assert(2 * N <= TH, "two threads per row");
   constexpr unsigned RB = N <= 256 ? 8 : (N <= 512 ? 9 : 10);
   constexpr unsigned RMASK = (1u << RB) - 1u;
   typedef TS v4 __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const bool has_row = tid < N;
+  const int row = tid >> 1, h = tid & 1;  // the two threads of a row take alternate 4-entry chunks
+  const bool has_row = row < N;
   bool used = !has_row;
   int mycol = N;  // the column this row pivots
-  TS* Ar = A + (has_row ? tid : 0) * LDP;
-  auto publish_key = [&](int c) {
+  TS* Ar = A + (has_row ? row : 0) * LDP;
+  // the key of column c comes from the thread that last updated the chunk holding it
+  auto publish_key = [&](int c, int owner) {
     unsigned k = 0u;
-    if (!used) k = (__float_as_uint((float)fabs((double)Ar[c])) & ~RMASK) | (RMASK - (unsigned)tid);
+    if (!used && h == owner) k = (__float_as_uint((float)fabs((double)Ar[c])) & ~RMASK) | (RMASK - (unsigned)row);
     k = seg_max_pow2<64>(k);
     if (lane == 0) s_key[(c & 1) * NW + wid] = (int)k;
   };
-  publish_key(0);
+  publish_key(0, 0);
   __syncthreads();
   for (int c = 0; c < N; ++c) {
     unsigned best = 0u;
@@ -280,14 +287,17 @@ __device__ __noinline__ void newton_solve_rows(TS* A, double* s_x, TS* s_pv, int
       s_perm[c] = p;
       s_pv[c] = pvc;
     }
-    if (tid == p) {
+    if (row == p) {
       used = true;
       mycol = c;
     }
+    const int j0 = c & ~3;
     if (!used) {
+      // both threads of the row read a_rc before either stores: they are neighbouring lanes of one
+      // wavefront, and the load precedes the stores in program order
       const TS l = Ar[c] * ((TS)1 / pvc);
 #pragma unroll 4
-      for (int j = c & ~3; j < LDP; j += 4) {
+      for (int j = j0 + 4 * h; j < LDP; j += 8) {
         v4* a = (v4*)(Ar + j);
         const v4 pv = *(const v4*)(Ap + j);
         v4 x = *a;
@@ -298,13 +308,13 @@ __device__ __noinline__ void newton_solve_rows(TS* A, double* s_x, TS* s_pv, int
         *a = x;
       }
     }
-    if (c + 1 < N) publish_key(c + 1);
+    if (c + 1 < N) publish_key(c + 1, (((c + 1) & ~3) - j0) >> 2);
     __syncthreads();
   }
   for (int c = N - 1; c >= 0; --c) {
     const double xc = (double)A[s_perm[c] * LDP + N] / (double)s_pv[c];
     if (tid == 0) s_x[c] = xc;
-    if (mycol < c) Ar[N] = fma(-Ar[c], (TS)xc, Ar[N]);
+    if (h == 0 && mycol < c) Ar[N] = fma(-Ar[c], (TS)xc, Ar[N]);
     __syncthreads();
   }
 }
@@ -318,12 +328,13 @@ using NewtonScalar =
     typename std::conditional<(size_t)N * ((N + 4) & ~3) * 8 <= 48 * 1024, double, float>::type;
 
 template <int D, int M>
-__global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeom g, double dt,
+__global__ __launch_bounds__(burgers_threads(BCfg<D, M>::N)) void burgers_predict_kernel(DevGeom g, double dt,
                                                                           const double* __restrict__ Qs,
                                                                           double* __restrict__ W, BurgersDev t,
                                                                           int64_t first, int64_t nel, int max_iter,
                                                                           int32_t* __restrict__ stats) {
   using C = BCfg<D, M>;
+  constexpr int TH = burgers_threads(C::N);
   constexpr int NS = C::NS, NT = C::NT, NB = C::NB, N = C::N, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
   const int64_t e = first + blockIdx.x;
   if (e >= nel) return;
@@ -338,12 +349,12 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
   __shared__ double s_x[N];
   __shared__ __align__(16) TS s_piv[LDP];
   __shared__ TS s_l[N];
-  __shared__ int s_key[2 * (kBurgersThreads / 64)];
+  __shared__ int s_key[2 * (TH / 64)];
   __shared__ int s_perm[N];
-  __shared__ double s_red[2][kBurgersThreads / 64];
+  __shared__ double s_red[2][TH / 64];
   __shared__ int64_t s_ge[NB];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  constexpr int NW = kBurgersThreads / 64;
+  constexpr int NW = TH / 64;
   if (tid < NB) {
     int base[3];
     elem_idx(g, e, base);
@@ -355,13 +366,13 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
     s_ge[tid] = elem_lin(g, base[0] + o[0], base[1] + o[1], base[2] + o[2]);
   }
   __syncthreads();
-  for (int x = tid; x < NB * NS; x += kBurgersThreads) {
+  for (int x = tid; x < NB * NS; x += TH) {
     const int r = x / NS, j = x % NS;
     s_q[x] = Qs[(int64_t)j * nel + s_ge[r]];
   }
-  for (int x = tid; x < N; x += kBurgersThreads) s_W[x] = 0.0;
+  for (int x = tid; x < N; x += TH) s_W[x] = 0.0;
   __syncthreads();
-  for (int x = tid; x < NB * NS; x += kBurgersThreads) {  // W^(0): the state held constant in time
+  for (int x = tid; x < NB * NS; x += TH) {  // W^(0): the state held constant in time
     const int r = x / NS, j = x % NS;
     s_W[r * NT + t.lift[j]] = s_q[x];
   }
@@ -372,7 +383,7 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
   while (it < max_iter && !converged) {
     ++it;
     newton_points<D, M>(t, s_W, s_wv, s_wf, s_fp);
-    for (int R = tid; R < N; R += kBurgersThreads)
+    for (int R = tid; R < N; R += TH)
       newton_row<D, M, TS>(t, c0, c1, c2, R, s_W, s_q, s_wv, s_wf, s_fp, s_A + R * LDP);
     __syncthreads();
     if constexpr (N > kRowsSolveMin)
@@ -381,7 +392,7 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
       newton_solve<N, TS>(s_A, s_x, s_l, s_piv, s_key);
     // update and convergence test (uniform across the workgroup)
     double md = 0.0, mw = 0.0;
-    for (int x = tid; x < N; x += kBurgersThreads) {
+    for (int x = tid; x < N; x += TH) {
       const double w = s_W[x] - s_x[x];
       s_W[x] = w;
       md = fmax(md, fabs(s_x[x]));
@@ -404,7 +415,7 @@ __global__ __launch_bounds__(kBurgersThreads) void burgers_predict_kernel(DevGeo
     __syncthreads();
   }
   const int centre = (NB - 1) / 2;
-  for (int k = tid; k < NT; k += kBurgersThreads) W[(int64_t)k * nel + e] = s_W[centre * NT + k];
+  for (int k = tid; k < NT; k += TH) W[(int64_t)k * nel + e] = s_W[centre * NT + k];
   if (tid == 0) {
     atomicMax(stats, it);
     if (!converged) atomicAdd(stats + 1, 1);
@@ -480,7 +491,7 @@ int burgers_predict_dm(const DevGeom& g, double dt, const double* Q, double* W, 
   constexpr int64_t kChunk = (int64_t)1 << 30;  // workgroups per launch at most
   for (int64_t first = 0; first < nel; first += kChunk) {
     const int64_t chunk = (nel - first < kChunk) ? nel - first : kChunk;
-    hipLaunchKernelGGL((burgers_predict_kernel<D, M>), dim3((unsigned)chunk), dim3(kBurgersThreads), 0,
+    hipLaunchKernelGGL((burgers_predict_kernel<D, M>), dim3((unsigned)chunk), dim3(burgers_threads(BCfg<D, M>::N)), 0,
                        (hipStream_t)stream, g, dt, Q, W, t, first, nel, max_iter, stats);
     const int err = (int)hipGetLastError();
     if (err) return err;
