@@ -5,7 +5,7 @@
 // LDS. Each Newton iteration
 //   1. evaluates w = Psi^T W_r at the volume and face Gauss points of every region element,
 //   2. projects F'(w) = w on the space-time basis (eq. Jacproj; quadrature once per mode),
-//   3. assembles one row of [J | R] per thread in the workgroup's LDS: time term and
+//   3. assembles one row of [J | R] per pair of lanes in the workgroup's LDS: time term and
 //      causal source from the exact tensors, volume flux residual by quadrature, volume Jacobian
 //      quasi-quadrature-free (sum_p beta^i_{k l p} F'_p with the exact triple products, eq.
 //      Jacobian2), face terms (Rusanov inside the region, own-trace physical flux on its boundary)
@@ -94,27 +94,32 @@ __device__ __noinline__ void newton_points(const BurgersDev& t, const double* s_
   __syncthreads();
 }
 
-// Row R = (r, k) of [J | R] (one thread): time term and causal source, volume flux residual by
-// quadrature, volume Jacobian from the triple products (eq. Jacobian2), face terms and their Jacobian
-// blocks by face quadrature.
+// Row R = (r, k) of [J | R], by two neighbouring lanes (h = 0, 1): time term and causal source
+// (h = 0), volume flux residual by quadrature and volume Jacobian from the triple products (eq.
+// Jacobian2) for the directions i = h, h + 2, ..., face terms and their Jacobian blocks by face
+// quadrature for the faces on side h of every direction. The two lanes' sums for the diagonal block
+// and the residual are added by a lane exchange and stored by lane h = 0; each lane stores the
+// neighbour blocks of its own faces.
 template <int D, int M, class TS>
-__device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, double c1, double c2, int R,
+__device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, double c1, double c2, int R, int h,
                                         const double* s_W, const double* s_q, const double* s_wv,
                                         const double* s_wf, const double* s_fp, TS* __restrict__ row) {
   using C = BCfg<D, M>;
   constexpr int NS = C::NS, NT = C::NT, N = C::N, NQ = C::NQ, NQF = C::NQF, NF = C::NF;
   const int r = R / NT, k = R % NT;
-  for (int j = 0; j < burgers_ldp(N); ++j) row[j] = (TS)0;
+  // (both lanes' zero stores precede every store of the row's values in their wavefront's order)
+  for (int j = h; j < burgers_ldp(N); j += 2) row[j] = (TS)0;
   double dg[NT];
   double res = 0.0;
 #pragma unroll
   for (int l = 0; l < NT; ++l) {
-    dg[l] = t.Tt[k * NT + l];
+    dg[l] = h == 0 ? t.Tt[k * NT + l] : 0.0;
     res = fma(dg[l], s_W[r * NT + l], res);
   }
-  for (int j = 0; j < NS; ++j) res = fma(-t.Cc[k * NS + j], s_q[r * NS + j], res);
+  if (h == 0)
+    for (int j = 0; j < NS; ++j) res = fma(-t.Cc[k * NS + j], s_q[r * NS + j], res);
 #pragma unroll 1
-  for (int i = 0; i < D; ++i) {
+  for (int i = h; i < D; i += 2) {
     const double cc = i == 0 ? c0 : (i == 1 ? c1 : c2);
     double v = 0.0;  // int int d_xi_i Psi_k F(w)
     const double* dw = t.dpsivw + ((size_t)i * NT + k) * NQ;
@@ -137,7 +142,7 @@ __device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, doubl
   const int d1 = (D == 2) ? r % 3 : (r / 3) % 3;
   const int d2 = r % 3;
 #pragma unroll 1
-  for (int f = 0; f < NF; ++f) {
+  for (int f = h; f < NF; f += 2) {
     const int i = f >> 1, fo = f ^ 1;
     const double cc = i == 0 ? c0 : (i == 1 ? c1 : c2);
     const double s = (f & 1) ? 1.0 : -1.0;
@@ -179,8 +184,13 @@ __device__ __forceinline__ void newton_row(const BurgersDev& t, double c0, doubl
     }
   }
 #pragma unroll
-  for (int l = 0; l < NT; ++l) row[r * NT + l] = (TS)dg[l];
-  row[N] = (TS)res;
+  for (int l = 0; l < NT; ++l) dg[l] += __shfl_xor(dg[l], 1, 64);
+  res += __shfl_xor(res, 1, 64);
+  if (h == 0) {
+#pragma unroll
+    for (int l = 0; l < NT; ++l) row[r * NT + l] = (TS)dg[l];
+    row[N] = (TS)res;
+  }
 }
 
 // Gaussian elimination with partial pivoting on the augmented N x (N + 1) matrix A held in LDS (rows
@@ -383,8 +393,8 @@ __global__ __launch_bounds__(burgers_threads(BCfg<D, M>::N)) void burgers_predic
   while (it < max_iter && !converged) {
     ++it;
     newton_points<D, M>(t, s_W, s_wv, s_wf, s_fp);
-    for (int R = tid; R < N; R += TH)
-      newton_row<D, M, TS>(t, c0, c1, c2, R, s_W, s_q, s_wv, s_wf, s_fp, s_A + R * LDP);
+    for (int R = tid >> 1; R < N; R += TH / 2)  // the two lanes of a row stay together
+      newton_row<D, M, TS>(t, c0, c1, c2, R, tid & 1, s_W, s_q, s_wv, s_wf, s_fp, s_A + R * LDP);
     __syncthreads();
     if constexpr (N > kRowsSolveMin)
       newton_solve_rows<N, TS>(s_A, s_x, s_l, s_perm, s_key);
