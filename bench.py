@@ -47,7 +47,8 @@ KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
                 "batch_predict_kernel": ["k_batch.hip"], "batch_correct_kernel": ["k_batch.hip"],
                 "tap_mfma_kernel": ["k_mfma.hip"], "brick_step_kernel": ["k_brick.hip"],
                 "burgers_predict_kernel": ["k_burgers.hip"], "burgers_correct_kernel": ["k_burgers.hip"],
-                "tap_zmarch_kernel": ["k_stencil3d.hip"]}
+                "tap_zmarch_kernel": ["k_stencil3d.hip"],
+                "tap_tblock_kernel": ["k_tblock.hip", "k_tblock.hpp"]}
 RECORD_TAG = "traffic-record: "
 
 
@@ -79,6 +80,8 @@ def dominant_kernel(info, opts, precision):
             return f"ridg::tap_mfma_kernel<{rows}, {cols}>"
         if opts.get("composite") == 2:
             return f"ridg::tap_zmarch_kernel<{info.theta}>"
+        if opts.get("composite") == 3:
+            return f"ridg::tap_tblock_kernel<{info.theta}>"
         if opts.get("composite"):
             return f"ridg::tap_update_kernel<{d}, {info.theta}, {info.theta}>"
         return f"ridg::predict_prefactored_kernel<{d}, {M}>"
@@ -320,6 +323,20 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     sim.enable_timing(False)
     nst = sim.newton_stats() if newton else None
     lat = np.array([a.elapsed_time(b) for a, b in zip(starts, ends)])
+    # four steps per launch (temporal blocking): its launches timed by HIP events on the library's
+    # stream, the per-step kernel being what the single steps above ran
+    tb_ms = None
+    if opts["composite"] == 3:
+        n_launch = 100
+        sim.set_state(q0_dev)
+        sim.step(8, wl.dt)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        sim.step(4 * n_launch, wl.dt)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        tb_ms = ev0.elapsed_time(ev1) / n_launch
     # throughput: the autotuned options, all timed steps in one call, from the initial state each trial
     sim.set_option(ridg.OPT_GRAPH, tuned["graph"])
     sim.set_option(ridg.OPT_FUSED, tuned["fused"])
@@ -342,7 +359,7 @@ def run_path(wl, precision, solver, refine, steps, warmup, label, trials=5, lat_
     pred_ms = tim.predict_ms / max(tim.steps, 1)
     corr_ms = tim.correct_ms / max(tim.steps, 1)
     return dict(info=info, wall=wall, walls=walls, lat=lat, pred_ms=pred_ms, corr_ms=corr_ms, q=q, opts=opts,
-                value=info.n_elements * info.theta_t * steps / wall, newton=nst)
+                value=info.n_elements * info.theta_t * steps / wall, newton=nst, tb_ms=tb_ms)
 
 
 def copy_reference(args):
@@ -536,10 +553,14 @@ def main():
         brick = bool(R["opts"].get("brick")) or best == "fp32"
         nbytes = info.bytes_composite if (comp or brick) else info.bytes_predict
         nflops = (info.flops_predict + info.flops_correct) if brick else (info.flops_composite if comp else info.flops_predict)
-        bw = nbytes / (R["pred_ms"] * 1e-3) / 1e9
-        tf = nflops / (R["pred_ms"] * 1e-3) / 1e12
-        kern = ("composite prediction+correction stencil" + (" marched along z through LDS" if comp == 2 else "")
-                if comp else "prediction (prefactored G)")
+        launch_ms = R["pred_ms"]
+        if comp == 3:  # one launch: four steps' flops, one read and one write of the state
+            nflops, launch_ms = 4 * info.flops_composite, R["tb_ms"]
+            roofline["avg_launch_ms"] = launch_ms
+        bw = nbytes / (launch_ms * 1e-3) / 1e9
+        tf = nflops / (launch_ms * 1e-3) / 1e12
+        kern = ("composite prediction+correction stencil" + (" marched along z through LDS" if comp == 2 else "") +
+                (", four steps per launch" if comp == 3 else "") if comp else "prediction (prefactored G)")
         mfma = bool(R["opts"].get("mfma"))
         if brick:
             kern = ("fused brick step (FP32 matrix-core predictions, FP64 correction)" if best == "fp32" else

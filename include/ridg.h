@@ -235,7 +235,9 @@ int ridg_get_timing(ridg_t* h, ridg_timing* out);
                                 state, K_o = sum D_t G_s (the predictions are not stored). 2: the same stencil
                                 marched along z by 16 x 16 tiles with three state planes in LDS (3D, orders
                                 2-3, n[0], n[1] multiples of 16, n[2] a multiple of 8 or at most 64); bitwise
-                                equal to 1 */
+                                equal to 1. 3: four steps per launch, each 16 x 16 tile advancing the region
+                                its result depends on in LDS (2D, FP64, n[0], n[1] multiples of 16; remaining
+                                steps and timed steps run as 1); bitwise equal to 1 */
 #define RIDG_OPT_MFMA 5      /* PREFACTORED: the prediction, correction or composite stencil as stacked-
                                 right-hand-side products on the FP64 matrix cores */
 #define RIDG_OPT_BRICK 6     /* PREFACTORED, 3D, orders 2-3, n[0] % 16 == 0, n[1] % 4 == 0, n[2] % 2 == 0: one

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <map>
 
+#include "k_tblock.hpp"
 #include "ridg_internal.hpp"
 
 using namespace ridg;
@@ -1003,6 +1004,18 @@ int ridg_step(ridg_t* h, int32_t n_steps, double dt) {
     h->cur ^= 1;
     return warn;
   }
+  if (h->opt_composite == 3 && !h->timing && n_steps >= kTBlockSteps) {  // kTBlockSteps steps per launch
+    const int nk = (int)h->host_ktaps.size() / 3;
+    if (!tblock_taps_supported(h->host_ktaps.data(), nk))
+      return fail(RIDG_E_UNSUPPORTED, "the composite taps reach beyond the temporally blocked kernel's window");
+    while (n_steps >= kTBlockSteps) {
+      int err = launch_tap_tblock(h->T.ns, h->geom, h->Q[h->cur], h->Q[1 - h->cur], h->Kc, h->host_ktaps.data(), nk,
+                                  h->stream);
+      if (err) return hip_fail(err, "temporally blocked composite launch");
+      h->cur ^= 1;
+      n_steps -= kTBlockSteps;
+    }
+  }
   if (h->opt_graph && !h->timing && n_steps >= 2) {
     if (h->graph_dt != dt) drop_graphs(h);
     h->graph_dt = dt;
@@ -1132,7 +1145,7 @@ int ridg_step_batch(ridg_t* const* handles, int32_t count, const double* dts, in
 
 int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
   if (!h) return fail(RIDG_E_INVAL, "handle is NULL");
-  const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : (option == RIDG_OPT_COMPOSITE ? 2 : 1);
+  const int64_t vmax = option == RIDG_OPT_PLAN_LAYOUT ? kLayouts - 1 : (option == RIDG_OPT_COMPOSITE ? 3 : 1);
   if (value < 0 || value > vmax) return fail(RIDG_E_INVAL, "option value out of range");
   if (h->P.solver == RIDG_SOLVER_NEWTON && value)
     return fail(RIDG_E_UNSUPPORTED, "RIDG_SOLVER_NEWTON has no execution options");
@@ -1161,6 +1174,9 @@ int ridg_set_option(ridg_t* h, int32_t option, int64_t value) {
       if (value == 2 && !zmarch_supported(h->P.d, h->T.ns, h->P.n[0], h->P.n[1], h->P.n[2]))
         return fail(RIDG_E_UNSUPPORTED, "the z-marched composite stencil needs 3D, order 2-3, n[0] and n[1] multiples "
                                         "of 16 and n[2] a multiple of 8 (or at most 64)");
+      if (value == 3 && (h->P.precision != RIDG_FP64 || !tblock_shape_supported(h->P.d, h->T.ns, h->P.n[0], h->P.n[1])))
+        return fail(RIDG_E_UNSUPPORTED, "the temporally blocked composite stencil needs 2D, FP64 and n[0], n[1] "
+                                        "multiples of 16");
       h->opt_composite = (int)value;
       break;
     case RIDG_OPT_MFMA:
@@ -1242,6 +1258,9 @@ int ridg_autotune(ridg_t* h, double dt, int32_t steps, double* best_ms_per_step)
       for (int c = 0; c < (pref ? 2 : 1); ++c)
         for (int m = 0; m < (pref ? 2 : 1); ++m) cands.push_back({g, l, 0, c, m, 0});
     if (pref && zmarch_supported(h->P.d, h->T.ns, h->P.n[0], h->P.n[1], h->P.n[2])) cands.push_back({g, 0, 0, 2, 0, 0});
+    if (pref && h->P.precision == RIDG_FP64 && tblock_shape_supported(h->P.d, h->T.ns, h->P.n[0], h->P.n[1]) &&
+        tblock_taps_supported(h->host_ktaps.data(), (int)h->host_ktaps.size() / 3))
+      cands.push_back({g, 0, 0, 3, 0, 0});
     if (h->brick_ok) cands.push_back({g, 0, 0, 0, 0, 1});
   }
   if (fusable && !f32_brick) cands.push_back({0, 0, 1, 0, 0, 0});

@@ -281,6 +281,8 @@ def test_full_step_counts_against_stored_oracle(name):
         variants += [[(ridg.OPT_PLAN_LAYOUT, 4)], [(ridg.OPT_PLAN_LAYOUT, 5)], [(ridg.OPT_PLAN_LAYOUT, 0)]]
     else:
         variants += [[(ridg.OPT_COMPOSITE, 1)], [(ridg.OPT_MFMA, 1)], [(ridg.OPT_GRAPH, 1)]]
+        if d == 2 and all(x % 16 == 0 for x in n):
+            variants.append([(ridg.OPT_COMPOSITE, 3)])  # four steps per launch
     for opts in variants:
         print(f"[gpu] {name} {opts}", flush=True)
         sim = ridg.Simulation(lib_problem(d, n, M, vel))
