@@ -96,8 +96,10 @@ def dominant_kernel(info, opts, precision):
             segw = 1
             while segw < (nt + 2) // 3:
                 segw *= 2
-            if lay == 5:  # static pivots
+            if lay == 5:  # static pivots (2D order 4: two rows per lane, the layout-3 geometry)
                 f32 = "true" if precision == "fp32" else "false"
+                if (d, M) == (2, 4):
+                    return f"ridg::predict_plans_sp_kernel<{d}, {M}, 2, {(nt + 1) // 2}, {f32}>"
                 return f"ridg::predict_plans_sp_kernel<{d}, {M}, {(nt + segw - 1) // segw}, {segw}, {f32}>"
             return f"ridg::predict_plans_nr_kernel<{d}, {M}, {(nt + segw - 1) // segw}, {segw}>"
         f32 = "true" if precision == "fp32" else "false"

@@ -1,5 +1,6 @@
 // Region solves by upwind elimination plans (Sec. 2.2 and Sec. 3), FP64 and FP32 with FP64 refinement.
 #include "kernels_common.hpp"
+#include "plans_nr.hpp"
 
 namespace ridg {
 
@@ -102,7 +103,8 @@ struct IpwL {
   static int run(int layout) {
     if (layout == 2) return 2 * PlanCfg<D, M, false>::S;
     if (layout == 3) return PlanCfg2R<D, M>::S;
-    if (layout == 4 || layout == kStaticPivotLayout) return PlanCfgDpp<D, M>::S;
+    if (layout == 4) return PlanCfgDpp<D, M>::S;
+    if (layout == kStaticPivotLayout) return PlanCfgSp<D, M>::S;
     return layout ? PlanCfg<D, M, true>::S : PlanCfg<D, M, false>::S;
   }
 };

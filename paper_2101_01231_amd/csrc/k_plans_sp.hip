@@ -1,6 +1,6 @@
 // Region solves by upwind elimination plans (Sec. 2.2 and Sec. 3) with static pivots (layout 5):
-// three rows per lane in power-of-two segments (the layout-4 geometry), FP64 or FP32 with
-// FP64-residual iterative refinement.
+// several rows per lane (the layout-4 geometry, or the layout-3 one at 2D order 4), FP64 or FP32
+// with FP64-residual iterative refinement.
 #include "plans_nr.hpp"
 
 namespace ridg {
@@ -11,7 +11,8 @@ struct launch_plans_spL {
                  const PlanTables& t, const PlanRec* plans, const int32_t* items, const int32_t* item_plan,
                  int64_t n_items, void* stream) {
     if (n_spacetime(D, M) > 64) return (int)hipErrorInvalidValue;
-    using C = PlanCfgDpp<D, M>;
+    using C = PlanCfgSp<D, M>;
+    if (n_items % C::S) return (int)hipErrorInvalidValue;  // the list is padded to whole wavefronts
     const int64_t per_block = (int64_t)C::WAVES * C::S;
     const int64_t blocks = (n_items + per_block - 1) / per_block;
     if (blocks == 0) return 0;

@@ -15,6 +15,14 @@ constexpr int kPivChunk = RIDG_PIV_CHUNK;  // pivot-row LDS reads between schedu
 #define RIDG_SP_LOOKAHEAD false
 #endif
 
+// Geometry of the static-pivot layout (5): the layout-4 segments, except at 2D order 4 (theta_T =
+// 20), where two rows per lane in 10-lane segments at three wavefronts per SIMD (FP64, 168 VGPRs)
+// measured 1.059 ms per prediction against 1.117 ms for three rows per lane in 8-lane segments at two
+// (FP32: 1.80 against 1.88 ms, at two wavefronts). Its segments per wavefront also set how the host
+// groups and pads the layout's work list.
+template <int D, int M>
+using PlanCfgSp = typename std::conditional<D == 2 && M == 4, PlanCfg2R<D, M>, PlanCfgDpp<D, M>>::type;
+
 // Per-lane state of the several-rows layouts: RPL rows of a region's block system in each lane of
 // a SEGW-lane segment; rows k + SEGW u (u < RPL) of every block, rows >= theta_T idle.
 template <class C>
@@ -431,9 +439,12 @@ predict_plans_nr_kernel(DevGeom g, double dt, const double* __restrict__ Q, doub
                                       &s_piv[wave][0][0]);
 }
 
-// Static pivots (layout 5): FP64 (F32 = false) or FP32 with `refine` FP64-residual sweeps.
+// Static pivots (layout 5): FP64 (F32 = false) or FP32 with `refine` FP64-residual sweeps. The FP64
+// kernel takes the geometry's register budget hint; the FP32 one, which also holds the refinement's
+// FP64 rows, keeps the compiler's choice (capped at three wavefronts it spills heavily).
 template <int D, int M, int RPL, int SEGW, bool F32>
-__global__ __launch_bounds__(256) void predict_plans_sp_kernel(DevGeom g, double dt, const double* __restrict__ Q,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(F32 ? 1 : PlanCfgNR<D, M, RPL, SEGW>::MIN_WAVES))) void predict_plans_sp_kernel(DevGeom g, double dt, const double* __restrict__ Q,
                                                                double* __restrict__ W, PlanTables t,
                                                                const PlanRec* __restrict__ plans,
                                                                const int32_t* __restrict__ items,
@@ -451,6 +462,7 @@ template <class C, int D, int M>
 static int launch_nr(const DevGeom& g, double dt, const double* Q, double* W, const PlanTables& t,
                      const PlanRec* plans, const int32_t* items, const int32_t* item_plan, int64_t n_items,
                      void* stream) {
+  if (n_items % C::S) return (int)hipErrorInvalidValue;  // the list is padded to whole wavefronts
   const int64_t per_block = (int64_t)C::WAVES * C::S;
   const int64_t blocks = (n_items + per_block - 1) / per_block;
   if (blocks == 0) return 0;
