@@ -11,7 +11,7 @@
 //      Jacobian2), face terms (Rusanov inside the region, own-trace physical flux on its boundary)
 //      and their Jacobian blocks by face quadrature,
 //   4. solves J delta = R by Gaussian elimination with partial pivoting in LDS (FP64 for the systems of
-//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2; two threads per row above 128 unknowns,
+//      up to 48 KB, FP32 above: 2D orders 3-4, 3D order 2; two threads per row above 64 unknowns,
 //      the update's 4-entry chunks spread over the workgroup below) and updates W <- W - delta,
 //      until max|delta| <= 1e-13 max(1, max|W|) or the iteration limit.
 // Only the centre's W is written. The Rusanov wave speed of a face is max(|mean q_a|, |mean q_b|)
@@ -32,16 +32,17 @@ constexpr double kNewtonTol = 1e-13;
 
 __host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
 
-// The elimination keeps each row with its own threads for systems above this size
+// The elimination keeps each row with two threads of its own for systems above this size
 // (newton_solve_rows) and spreads the 4-entry chunks of the rank-1 update over the workgroup below
-// it (newton_solve).
-constexpr int kRowsSolveMin = 128;
-
-// Threads of a region's workgroup: 512 where the region system's LDS leaves room for one workgroup
-// per CU (two wavefronts per SIMD, two threads per row in the elimination), 256 otherwise (several
-// workgroups per CU). Measured per Burgers step at 128^2 with two threads per row against one:
-// order 4 (N = 180), 79.4 against 89.5 ms; at 512 threads, order 3 (N = 90) took 18.3 against 10.5 ms.
-__host__ __device__ constexpr int burgers_threads(int n) { return n > kRowsSolveMin ? 512 : 256; }
+// it (newton_solve). Measured per Burgers step at 128^2: N = 90 (2D order 3), 9.6 against 10.4 ms;
+// N = 36 (2D order 2), 2.6 against 2.3 ms.
+constexpr int kRowsSolveMin = 64;
+// Threads of a region's workgroup: 512 above this size, where the region system's LDS leaves room
+// for one workgroup per CU (two wavefronts per SIMD), 256 below (several workgroups per CU).
+// Measured per Burgers step at 128^2: order 4 (N = 180) 79.4 ms at 512 threads against 89.5 ms at
+// 256 (one thread per row); at 512 threads, order 3 (N = 90) took 18.3 against 10.5 ms.
+constexpr int kWideMin = 128;
+__host__ __device__ constexpr int burgers_threads(int n) { return n > kWideMin ? 512 : 256; }
 
 // Row stride of the augmented matrix in LDS: a multiple of 4 entries (the updates move 4-entry
 // chunks); for the one-row-per-thread elimination also an odd number of chunks, so that the 16-byte
