@@ -48,7 +48,8 @@ KERNEL_UNITS = {"predict_plans2_kernel": ["k_plans2.hip"],
                 "tap_mfma_kernel": ["k_mfma.hip"], "brick_step_kernel": ["k_brick.hip"],
                 "burgers_predict_kernel": ["k_burgers.hip"], "burgers_correct_kernel": ["k_burgers.hip"],
                 "tap_zmarch_kernel": ["k_stencil3d.hip"],
-                "tap_tblock_kernel": ["k_tblock.hip", "k_tblock.hpp"]}
+                "tap_tblock_kernel": ["k_tblock.hip", "k_tblock.hpp"],
+                "tap_z2_kernel": ["k_stencil3d.hip", "k_stencil3d.hpp"]}
 RECORD_TAG = "traffic-record: "
 
 
@@ -65,8 +66,8 @@ def kernel_source_hash(kernel):
     return h.hexdigest()[:16]
 
 
-def dominant_kernel(info, opts, precision):
-    """Name (as the profiler prints it) of the kernel that runs the prediction stage."""
+def dominant_kernel(info, opts, precision, n=None):
+    """Name (as the profiler prints it) of the kernel that runs the prediction stage (n: the mesh)."""
     from paper_2101_01231_amd import ridg
     d, M = _dim_order(info)
     if info.solver == ridg.SOLVER_NEWTON:
@@ -82,6 +83,8 @@ def dominant_kernel(info, opts, precision):
             return f"ridg::tap_zmarch_kernel<{info.theta}>"
         if opts.get("composite") == 3:
             return f"ridg::tap_tblock_kernel<{info.theta}>"
+        if opts.get("composite") and d == 3 and info.theta <= 10 and n is not None and n[2] % 2 == 0:
+            return f"ridg::tap_z2_kernel<{info.theta}>"  # two z-neighbours per thread
         if opts.get("composite"):
             return f"ridg::tap_update_kernel<{d}, {info.theta}, {info.theta}>"
         return f"ridg::predict_prefactored_kernel<{d}, {M}>"
@@ -544,7 +547,7 @@ def main():
                 "correction": {"achieved_tflops": info.flops_correct / (R["corr_ms"] * 1e-3) / 1e12,
                                "achieved_gbs": info.bytes_correct / (R["corr_ms"] * 1e-3) / 1e9,
                                "avg_ms": R["corr_ms"]}}
-    kern_name = dominant_kernel(info, R["opts"], best)
+    kern_name = dominant_kernel(info, R["opts"], best, wl.n)
     tr = traffic_from_profiles(kern_name)
     roofline["kernel_name"] = kern_name
     roofline["traffic"] = tr["bytes"] if tr else None

@@ -1012,6 +1012,20 @@ void build_composite(const Problem& P, const Prefactored& G, const TapOperator& 
           for (int c = 0; c < ns; ++c) K[(size_t)r * ns + c] += dv * Gs[(size_t)k * ns + c];
         }
     }
+  // column order: offsets sorted by (x, y, z), so the taps of one (x, y) column follow each other
+  // with increasing z (the 3D kernel that advances two z-neighbours per thread reuses one element's
+  // load for the other's next tap); every composite kernel sums its taps in this order
+  std::vector<size_t> perm(out->offs.size());
+  for (size_t q = 0; q < perm.size(); ++q) perm[q] = q;
+  std::sort(perm.begin(), perm.end(), [&](size_t a, size_t b) { return out->offs[a] < out->offs[b]; });
+  std::vector<std::array<int, 3>> offs(perm.size());
+  std::vector<double> A(out->A.size());
+  for (size_t q = 0; q < perm.size(); ++q) {
+    offs[q] = out->offs[perm[q]];
+    std::copy_n(&out->A[perm[q] * (size_t)ns * ns], (size_t)ns * ns, &A[q * (size_t)ns * ns]);
+  }
+  out->offs.swap(offs);
+  out->A.swap(A);
 }
 
 

@@ -8,6 +8,7 @@
 // tap. Each thread then applies all taps to its element from LDS; the operator K (wave-uniform) comes
 // through scalar loads.
 #include "kernels_common.hpp"
+#include "k_stencil3d.hpp"
 
 namespace ridg {
 
@@ -103,6 +104,112 @@ static int zmarch_ns(const DevGeom& g, const double* in, double* out, const doub
   hipLaunchKernelGGL((tap_zmarch_kernel<NS>), dim3((unsigned)blocks), dim3(kZT * kZT), 0, (hipStream_t)stream, g,
                      in, out, A, tp, ntaps, zm);
   return (int)hipGetLastError();
+}
+
+// The one-element-per-thread composite step for two z-neighbours (x, y, 2 z2) and (x, y, 2 z2 + 1)
+// per thread. The taps come in column order (same (x, y) offset, increasing z), so the value that the
+// upper element reads for tap (ox, oy, oz) is the one the lower element needs for the column's next
+// tap (ox, oy, oz + 1): it is kept instead of loaded again, and a column of three taps costs four
+// loads of the theta coefficients instead of six. (At 128^3, order 3, the one-element kernel keeps
+// the texture-address unit busy 91% of the time and the VALU 55%.) Each element sums its taps in list
+// order with tap_update_elem's fused multiply-adds, so the result is bitwise the same.
+//
+// Where n1 is a multiple of 8 and a band of n1 / 8 rows holds whole workgroups (`banded`), the
+// workgroups of each XCD (workgroup b runs on XCD b % 8) take one such band in y, band-plane after
+// band-plane along z, so the neighbours they read one and two planes back are more often still in
+// that XCD's L2: at 128^3, order 3, 1.52 against 1.78 GB fetched per launch and 0.273 against 0.285
+// ms; otherwise consecutive pairs of planes are spread over the XCDs in contiguous ranges.
+template <int NS>
+__global__ __launch_bounds__(256) void tap_z2_kernel(DevGeom g, const double* __restrict__ in,
+                                                     double* __restrict__ out, const double* __restrict__ A,
+                                                     TapsN taps, int ntaps, int banded) {
+  const int64_t plane = (int64_t)g.n0 * g.n1, nel = plane * g.n2;
+  int64_t e0;
+  if (banded) {
+    const int band = g.n1 / 8;
+    const int64_t per_plane = (int64_t)g.n0 * band / 256;  // workgroups per band-plane
+    const int xcd = (int)(blockIdx.x % 8);
+    const int64_t j = blockIdx.x / 8;
+    const int64_t zp = j / per_plane, r = j - zp * per_plane;
+    const int64_t local = r * 256 + threadIdx.x;
+    const int x = (int)(local % g.n0), y = xcd * band + (int)(local / g.n0);
+    e0 = (int64_t)x + (int64_t)g.n0 * ((int64_t)y + (int64_t)g.n1 * (2 * zp));
+  } else {
+    const int64_t p = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    if (p >= nel / 2) return;
+    e0 = p % plane + 2 * plane * (p / plane);
+  }
+  const int64_t e1 = e0 + plane;
+  int idx[3];
+  elem_idx(g, e0, idx);
+  double acc0[NS], acc1[NS], up[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) acc0[k] = acc1[k] = up[k] = 0.0;
+  int px = 0, py = 0, pz = 0;
+  bool have = false;  // `up` holds the value at (px, py, pz + 1)
+  for (int t = 0; t < ntaps; ++t) {
+    const int ox = taps.off[t][0], oy = taps.off[t][1], oz = taps.off[t][2];
+    double x0[NS];
+    if (have && ox == px && oy == py && oz == pz + 1) {
+#pragma unroll
+      for (int l = 0; l < NS; ++l) x0[l] = up[l];
+    } else {
+      const int64_t s0 = elem_lin(g, idx[0] + ox, idx[1] + oy, idx[2] + oz);
+#pragma unroll
+      for (int l = 0; l < NS; ++l) x0[l] = in[(int64_t)l * nel + s0];
+    }
+    const int64_t s1 = elem_lin(g, idx[0] + ox, idx[1] + oy, idx[2] + oz + 1);
+#pragma unroll
+    for (int l = 0; l < NS; ++l) up[l] = in[(int64_t)l * nel + s1];
+    px = ox;
+    py = oy;
+    pz = oz;
+    have = true;
+    const double* At = A + (size_t)t * NS * NS;
+#pragma unroll
+    for (int k = 0; k < NS; ++k)
+#pragma unroll
+      for (int l = 0; l < NS; ++l) {
+        const double a = At[k * NS + l];
+        acc0[k] = fma(a, x0[l], acc0[k]);
+        acc1[k] = fma(a, up[l], acc1[k]);
+      }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    out[(int64_t)k * nel + e0] = in[(int64_t)k * nel + e0] + acc0[k];
+    out[(int64_t)k * nel + e1] = in[(int64_t)k * nel + e1] + acc1[k];
+  }
+}
+
+bool z2_supported(int d, int ns, int n2) {
+  return d == 3 && n2 % 2 == 0 && (ns == 1 || ns == 4 || ns == 10);  // order 4 and up: 168+ VGPRs
+}
+
+template <int NS>
+static int z2_ns(const DevGeom& g, const double* in, double* out, const double* A, const int32_t* taps, int ntaps,
+                 void* stream) {
+  if (ntaps < 1 || ntaps > kMaxTapUpdate || in == out) return (int)hipErrorInvalidValue;
+  TapsN tp;
+  for (int t = 0; t < kMaxTapUpdate; ++t)
+    for (int i = 0; i < 3; ++i) tp.off[t][i] = (t < ntaps) ? (int8_t)taps[3 * t + i] : 0;
+  const int64_t nel = (int64_t)g.n0 * g.n1 * g.n2;
+  // bands: whole workgroups per band-plane, and the grid (nel / 512 workgroups) a multiple of 8
+  const int banded = g.n1 % 8 == 0 && ((int64_t)g.n0 * (g.n1 / 8)) % 256 == 0 ? 1 : 0;
+  hipLaunchKernelGGL((tap_z2_kernel<NS>), dim3(grid_for(nel / 2, 256)), dim3(256), 0, (hipStream_t)stream, g, in, out,
+                     A, tp, ntaps, banded);
+  return (int)hipGetLastError();
+}
+
+int launch_tap_z2(int ns, const DevGeom& g, const double* in, double* out, const double* A, const int32_t* taps,
+                  int ntaps, void* stream) {
+  if (!z2_supported(g.d, ns, g.n2)) return (int)hipErrorInvalidValue;
+  switch (ns) {
+    case 1: return z2_ns<1>(g, in, out, A, taps, ntaps, stream);
+    case 4: return z2_ns<4>(g, in, out, A, taps, ntaps, stream);
+    case 10: return z2_ns<10>(g, in, out, A, taps, ntaps, stream);
+    default: return (int)hipErrorInvalidValue;
+  }
 }
 
 bool zmarch_supported(int d, int ns, int n0, int n1, int n2) {

@@ -83,10 +83,20 @@ def test_dominant_kernel_names_follow_the_options():
     assert bench.dominant_kernel(Info(), {"plan_layout": 4}, "fp64") == "ridg::predict_plans_nr_kernel<2, 4, 3, 8>"
     assert bench.dominant_kernel(Info(), {"plan_layout": 3}, "fp64") == "ridg::predict_plans_nr_kernel<2, 4, 2, 10>"
     assert bench.dominant_kernel(Info(), {"plan_layout": 0}, "fp32") == "ridg::predict_plans_kernel<2, 4, false, true>"
+    # static pivots at 2D order 4: two rows per lane in 10-lane segments
+    assert bench.dominant_kernel(Info(), {"plan_layout": 5}, "fp64") == "ridg::predict_plans_sp_kernel<2, 4, 2, 10, false>"
 
     class Info3:
         theta, theta_t, solver = 10, 15, 1  # 3D order 3, PREFACTORED
 
     assert bench.dominant_kernel(Info3(), {"composite": 1}, "fp64") == "ridg::tap_update_kernel<3, 10, 10>"
+    # two z-neighbours per thread where n[2] is even; one element per thread otherwise
+    assert bench.dominant_kernel(Info3(), {"composite": 1}, "fp64", (128, 128, 128)) == "ridg::tap_z2_kernel<10>"
+    assert bench.dominant_kernel(Info3(), {"composite": 1}, "fp64", (12, 12, 13)) == "ridg::tap_update_kernel<3, 10, 10>"
+
+    class Info2:
+        theta, theta_t, solver = 6, 10, 1  # 2D order 3, PREFACTORED
+
+    assert bench.dominant_kernel(Info2(), {"composite": 3}, "fp64", (256, 256)) == "ridg::tap_tblock_kernel<6>"
     assert bench.dominant_kernel(Info3(), {"composite": 1, "mfma": 1}, "fp64") == "ridg::tap_mfma_kernel<10, 10>"
     assert bench.dominant_kernel(Info3(), {"mfma": 1}, "fp64") == "ridg::tap_mfma_kernel<15, 10>"

@@ -48,3 +48,17 @@ def test_zmarch_rejected_where_not_applicable():
     with pytest.raises(ridg.RidgError):
         sim.set_option(ridg.OPT_COMPOSITE, 2)
     sim.close()
+
+
+def test_banded_two_plane_kernel_small_mesh():
+    """On a mesh whose y-bands hold whole workgroups (64 x 32 x 4) the composite step runs two
+    z-neighbours per thread with the XCD band mapping: bitwise the z-marched kernel's result (same
+    taps, same order), and the prediction + correction path's to rounding."""
+    n, M, v = (64, 32, 4), 3, (0.8, -0.6, 0.4)
+    q0 = I.random_state(3, n, M, seed=131)
+    dt = 0.45 / max(n) / max(abs(x) for x in v)
+    print(f"[gpu] banded z2 n={n}", flush=True)
+    got = _run(n, M, v, q0, dt, 3, 1)
+    assert np.array_equal(got, _run(n, M, v, q0, dt, 3, 2))
+    ref = _run(n, M, v, q0, dt, 3, 0)
+    assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref)
