@@ -17,10 +17,6 @@
 
 #include "k_stencil3d.hpp"
 #include "k_tblock.hpp"
-
-#ifndef RIDG_Z2
-#define RIDG_Z2 1
-#endif
 #include "ridg_internal.hpp"
 
 using namespace ridg;
@@ -912,7 +908,7 @@ static int direct_step(ridg_t* h, double dt) {
                                 h->stream);
     if (err) return hip_fail(err, "z-marched composite launch");
   } else if (pref && h->opt_composite) {  // prediction and correction composed into one stencil
-    const bool z2 = !mfma && RIDG_Z2 && z2_supported(P.d, h->T.ns, P.n[2]);  // 3D: two z-neighbours per thread
+    const bool z2 = !mfma && z2_supported(P.d, h->T.ns, P.n[2]);  // 3D: two z-neighbours per thread
     int err = mfma ? launch_tap_mfma(P.d, P.M, kMfmaComposite, h->geom, h->Q[h->cur], h->Q[h->cur],
                                             h->Q[1 - h->cur], h->Fk, h->host_ktaps.data(), nk, h->stream)
               : z2 ? launch_tap_z2(h->T.ns, h->geom, h->Q[h->cur], h->Q[1 - h->cur], h->Kc, h->host_ktaps.data(), nk,
